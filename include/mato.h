@@ -1,0 +1,185 @@
+/*
+ * mato.h -- C ABI of the MI355X (gfx950) alternating-minimisation multi-agent
+ * trajectory optimiser of Rastgar et al., "GPU Accelerated Convex
+ * Approximations for Fast Multi-Agent Trajectory Optimization" (arXiv 2011.04240).
+ *
+ * The library implements the while-loop of Algorithm 1 (Sec. III-A): per
+ * iteration it builds the linear term rho A_fc^T b_fc of eq. (cost_step_x),
+ * applies the precomputed inverse of the KKT matrix of eq. (kkt_step_x) to the
+ * x, y and z right-hand sides, forms all pairwise position differences, takes
+ * the closed-form alpha/beta projection of eq. (sphere_project) and the d step of
+ * eq. (step_d) with d >= 1, and updates the multipliers, eq. (lag_update).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a mato_status: 0 = success, < 0 = error (nothing
+ *     was changed unless stated), > 0 = warning (results are valid).
+ *     mato_last_error() returns a thread-local message for the last failure.
+ *   - Pointers to caller data may be host or device pointers (HIP unified
+ *     addressing decides); the caller owns them and may reuse them as soon as
+ *     the call returns.  Handles own their device memory; *_destroy frees it.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the legacy
+ *     default stream).  Calls that return data to the caller synchronise that stream.
+ *   - No exception crosses the ABI.  Handles are not thread-safe: one thread
+ *     drives a handle at a time.
+ *   - Agents are indexed 0..n-1; pair p = (i, j), i < j, is numbered in the row
+ *     order of A_fc, eq. (A_f): p(i, j) = i n - i (i + 1) / 2 + (j - i - 1).
+ *   - Coefficient arrays are [agent][axis][coef] (axis order x, y, z); pairwise
+ *     arrays (multipliers, d e) are [pair][time][axis].
+ */
+#ifndef MATO_H
+#define MATO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mato_status;
+
+#define MATO_OK                   0
+#define MATO_ERR_INVALID_ARG     -1  /* a size, pointer or parameter out of range            */
+#define MATO_ERR_OUT_OF_MEMORY   -2  /* device allocation failed or HBM budget exceeded      */
+#define MATO_ERR_SINGULAR        -3  /* zero pivot or condition estimate above 1e14           */
+#define MATO_ERR_NONFINITE       -4  /* NaN or Inf in inputs or state                        */
+#define MATO_ERR_HIP             -5  /* a HIP runtime call failed                            */
+#define MATO_ERR_UNSUPPORTED     -6  /* valid request this build does not handle (e.g. n > MATO_MAX_AGENTS) */
+#define MATO_ERR_NOT_FOUND       -7  /* unknown request or slot id                            */
+#define MATO_WARN_NOT_CONVERGED   1  /* iteration cap reached before the residual tolerance  */
+
+#define MATO_MAX_AGENTS 160          /* largest n: the pairwise stage keeps one instant of all
+                                        n(n-1)/2 pairs in LDS                                  */
+
+/* Trajectory basis of eq. (param): Bernstein polynomials of degree n_coef-1 over
+ * [0, t_final] seconds, sampled at T uniformly spaced instants including both ends. */
+typedef enum { MATO_BASIS_BERNSTEIN = 0 } mato_basis_kind;
+typedef struct {
+    int32_t kind;      /* mato_basis_kind                                  */
+    int32_t n_coef;    /* coefficients per agent and axis (n_v), 6..16     */
+    double  t_final;   /* horizon in seconds, > 0                          */
+} mato_basis;
+
+/* Arithmetic of the per-iteration path.  The offline inverse is always FP64.
+ *   MATO_FP64        : every stage in FP64 (reference precision on the GPU).
+ *   MATO_FP32        : every stage in FP32; the inverse is rounded to FP32.
+ *   MATO_BF16_REFINED: FP32 state; the inverse product runs on BF16 MFMA with FP32
+ *                      accumulation over a two-term BF16 split of the inverse and of
+ *                      the right-hand side, followed by an FP64 residual correction. */
+typedef enum { MATO_FP64 = 0, MATO_FP32 = 1, MATO_BF16_REFINED = 2 } mato_precision;
+
+typedef struct mato_plan_s*   mato_plan;    /* K^{-1} of eq. (kkt_step_x) for one (n, T, basis, rho) */
+typedef struct mato_batch_s*  mato_batch;   /* one or more independent problems iterated together    */
+typedef struct mato_server_s* mato_server;  /* continuous-batching request loop                      */
+
+const char* mato_last_error(void);
+const char* mato_version(void);
+
+/* ---------------------------------------------------------------- plans ---
+ * Offline step (Remarks 1-2): builds P, P-dot, P-ddot (eq. (param)), the
+ * boundary matrix A, the KKT matrix
+ *     K = [[Q_x + rho A_fc^T A_fc, A_eq^T], [A_eq, 0]],   Q_x = diag(Pddot^T Pddot),
+ * of eq. (kkt_step_x) and inverts it on the device in FP64 (Gauss-Jordan with
+ * partial pivoting).  K depends on n, T, the basis and rho only; a (= l_xy) and
+ * b (= l_z), the spheroid dimensions of eq. (sphere_proposed), are stored for the
+ * pairwise stage.  The plan is immutable and may be shared by any number of batches.
+ * Errors: INVALID_ARG (n < 2, T < n_coef, n_coef outside 6..16, a, b, rho or t_final
+ * not > 0, unknown basis or precision), UNSUPPORTED (n > MATO_MAX_AGENTS),
+ * SINGULAR, OUT_OF_MEMORY, HIP. */
+mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis,
+                             double a, double b, double rho, int32_t precision,
+                             void* hip_stream, mato_plan* out);
+void        mato_plan_destroy(mato_plan plan);
+
+/* Sizes and diagnostics: n, T, n_coef, precision; cond = ||K||_1 ||K^{-1}||_1 (FP64). */
+mato_status mato_plan_info(mato_plan plan, int32_t* n, int32_t* T, int32_t* n_coef,
+                           int32_t* precision, double* cond);
+
+/* Copies the FP64 inverse of K, (17n x 17n for n_coef = 11) row-major, unknowns ordered
+ * [c (agent-major, n*n_coef); nu (agent-major, 6n)], into `kinv` (host or device).  */
+mato_status mato_plan_inverse(mato_plan plan, double* kinv);
+
+/* --------------------------------------------------------------- batches ---
+ * A batch holds `count` independent problems, problem q using plans[q]; problems
+ * with the same plan share one K^{-1} and are advanced together as one
+ * matrix-matrix product per iteration.  All plans must have the same precision.
+ * starts/goals: 3 doubles per agent per problem, problems concatenated in order
+ * ([problem][agent][x,y,z]); velocities and accelerations at both ends are zero.
+ * Creation runs the initialisation of Algorithm 1: multipliers 0, coefficients
+ * from the boundary-only minimum-acceleration problem, then alpha, beta and
+ * d = max(1, d*) at those positions.  Errors: INVALID_ARG, NONFINITE (starts/goals),
+ * OUT_OF_MEMORY, HIP. */
+mato_status mato_batch_create(int32_t count, const mato_plan* plans,
+                              const double* starts, const double* goals,
+                              void* hip_stream, mato_batch* out);
+void        mato_batch_destroy(mato_batch batch);
+
+/* Enqueue k iterations of Algorithm 1 for every problem not yet converged
+ * (asynchronous).  A problem is converged once max_{p,t} ||f_c|| < tol, tested
+ * after every iteration on the device (tol <= 0: never).  Iterations are replayed
+ * from a captured HIP graph when use_graph != 0. */
+mato_status mato_batch_step(mato_batch batch, int32_t k, double tol, int32_t use_graph);
+
+/* Run up to `iters` iterations, checking convergence on the host every
+ * `check_every` iterations (>= 1) and stopping once every problem has converged.
+ * Returns NOT_CONVERGED if any problem reached the cap. */
+mato_status mato_batch_run(mato_batch batch, int32_t iters, double tol, int32_t check_every);
+
+mato_status mato_batch_sync(mato_batch batch);
+
+/* Number of iterations problem q has taken, and whether it converged. */
+mato_status mato_batch_status(mato_batch batch, int32_t q, int32_t* iters, int32_t* converged);
+
+/* Coefficients of problem q, [agent][axis][coef], converted to double. */
+mato_status mato_batch_coeffs(mato_batch batch, int32_t q, double* c);
+
+/* Per-iteration history of problem q: max and RMS of ||f_c||_2 over pairs and
+ * instants (metres) and the smoothness cost sum ||p-ddot||^2 of eq. (cost_proposed).
+ * Writes min(cap, iterations) entries; any output pointer may be NULL. */
+mato_status mato_batch_residuals(mato_batch batch, int32_t q, double* r_max, double* r_rms,
+                                 double* cost, int32_t cap, int32_t* n_written);
+
+/* Checkpoint / parity hooks.  The state of problem q between iterations is
+ * (c, lambda, d e): multipliers and the projected points of eq. (b_f)
+ * (b_fc = d e - lambda / rho).  Buffers are in the batch's precision (float for
+ * MATO_FP32 / MATO_BF16_REFINED, double for MATO_FP64): c [n][3][n_coef],
+ * lambda and proj [n_pairs][T][3].  get_state's `proj`, `d` and `X` need
+ * mato_batch_debug(batch, 1) before the iteration that produced them
+ * (d: [n_pairs][T]; X: positions [n][3][T]); any output pointer may be NULL.
+ * set_state rebuilds the linear term from (lambda, proj); c is kept for reporting. */
+mato_status mato_batch_debug(mato_batch batch, int32_t enable);
+mato_status mato_batch_get_state(mato_batch batch, int32_t q, void* c, void* lambda,
+                                 void* proj, void* d, void* X);
+mato_status mato_batch_set_state(mato_batch batch, int32_t q, const void* c,
+                                 const void* lambda, const void* proj);
+/* Linear term g = rho A_fc^T b_fc currently held for problem q, [n][3][n_coef]. */
+mato_status mato_batch_linear_term(mato_batch batch, int32_t q, void* g);
+
+/* Pairwise-stage launch shape: pair-instants per workgroup (target) and threads per
+ * workgroup (256, 512 or 1024).  mato_batch_autotune times candidate shapes on the
+ * batch's own problems before it is used (state is re-initialised afterwards) and
+ * keeps the fastest; results are cached in the file named by MATO_TUNE_CACHE.  */
+mato_status mato_batch_set_tiles(mato_batch batch, int32_t items_per_wg, int32_t threads);
+mato_status mato_batch_get_tiles(mato_batch batch, int32_t* items_per_wg, int32_t* threads);
+mato_status mato_batch_autotune(mato_batch batch, int32_t* items_per_wg, int32_t* threads);
+
+/* Device time (ms, HIP events on the batch stream) of the last mato_batch_step or
+ * mato_batch_run call, and of its pairwise launches alone (summed); enabled by
+ * mato_batch_timing(batch, 1). */
+mato_status mato_batch_timing(mato_batch batch, int32_t enable);
+mato_status mato_batch_last_times(mato_batch batch, double* total_ms, double* pairwise_ms,
+                                  int32_t* pairwise_launches);
+
+/* ------------------------------------------------------ single problem ---
+ * Convenience wrappers: a solve is a batch of one (same handle type). */
+typedef struct mato_batch_s* mato_solve;
+mato_status mato_solve_run(mato_plan plan, const double* starts, const double* goals,
+                           int32_t iters, double tol, int32_t check_every, mato_solve* out);
+mato_status mato_solve_coeffs(mato_solve s, double* c);
+mato_status mato_residuals(mato_solve s, double* r_max, double* r_rms, double* cost,
+                           int32_t cap, int32_t* n_written);
+void        mato_solve_destroy(mato_solve s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MATO_H */

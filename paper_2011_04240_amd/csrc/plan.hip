@@ -1,0 +1,423 @@
+// Offline plan (Remarks 1-2, Sec. III-B): trajectory basis of eq. (param), the
+// KKT matrix of eq. (kkt_step_x) and its FP64 inverse, computed once per
+// (n, T, basis, rho) and shared by every problem with those sizes.
+//
+// The inverse is taken on the device by Gauss-Jordan elimination with partial
+// pivoting on the augmented matrix [K | I]; the c-rows [K11^{-1} | K12^{-1}] are
+// then stored in the arithmetic of the per-iteration product (FP32, a two-term
+// BF16 split, or FP64).
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+
+namespace mato {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+const char* last_error() { return g_err; }
+
+// ------------------------------------------------------------ basis (host) ---
+static double binom(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+static double bern(int deg, int j, double tau) {
+    if (j < 0 || j > deg) return 0.0;
+    return binom(deg, j) * std::pow(tau, j) * std::pow(1.0 - tau, deg - j);
+}
+
+// P, P-dot, P-ddot (T x nv) of a degree nv-1 Bernstein basis on tau_k = k/(T-1),
+// derivatives in physical time t = t_final * tau.
+static void bernstein_basis(int nv, int T, double tf, std::vector<double>& P,
+                            std::vector<double>& Pd, std::vector<double>& Pdd) {
+    const int N = nv - 1;
+    P.assign((size_t)T * nv, 0.0);
+    Pd.assign((size_t)T * nv, 0.0);
+    Pdd.assign((size_t)T * nv, 0.0);
+    for (int k = 0; k < T; ++k) {
+        const double tau = (double)k / (double)(T - 1);
+        for (int j = 0; j < nv; ++j) {
+            P[(size_t)k * nv + j] = bern(N, j, tau);
+            Pd[(size_t)k * nv + j] = N * (bern(N - 1, j - 1, tau) - bern(N - 1, j, tau)) / tf;
+            Pdd[(size_t)k * nv + j] = N * (N - 1) *
+                (bern(N - 2, j - 2, tau) - 2.0 * bern(N - 2, j - 1, tau) + bern(N - 2, j, tau)) / (tf * tf);
+        }
+    }
+}
+
+static void gram(const std::vector<double>& X, int T, int nv, std::vector<double>& G) {
+    G.assign((size_t)nv * nv, 0.0);
+    for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < T; ++k) s += X[(size_t)k * nv + a] * X[(size_t)k * nv + b];
+            G[(size_t)a * nv + b] = s;
+        }
+}
+
+// ------------------------------------------------------ device kernels ---
+// K of eq. (kkt_step_x), unknowns [c (agent-major); nu (agent-major)]:
+//   H_(i,k),(j,l) = delta_ij Pdd^T Pdd[k][l] + rho (n delta_ij - 1) P^T P[k][l]
+// (the collision Gram A_fc^T A_fc = (n I - 1 1^T) (x) P^T P), A_eq = I (x) A.
+// Written into the left half of the augmented matrix W = [K | I].
+__global__ void assemble_kkt(double* __restrict__ W, int n, int nv, int nb, double rho,
+                             const double* __restrict__ PtP, const double* __restrict__ PddtPdd,
+                             const double* __restrict__ A) {
+    const int N = n * (nv + nb);
+    const size_t total = (size_t)N * 2 * N;
+    const int nc = n * nv;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / (2 * N)), c = (int)(e % (2 * N));
+        double v = 0.0;
+        if (c >= N) {
+            v = (c - N == r) ? 1.0 : 0.0;
+        } else if (r < nc && c < nc) {
+            const int i = r / nv, k = r % nv, j = c / nv, l = c % nv;
+            v = rho * ((i == j ? n : 0) - 1) * PtP[k * nv + l];
+            if (i == j) v += PddtPdd[k * nv + l];
+        } else if (r < nc && c >= nc) {
+            const int i = r / nv, k = r % nv, j = (c - nc) / nb, b = (c - nc) % nb;
+            v = (i == j) ? A[b * nv + k] : 0.0;
+        } else if (r >= nc && c < nc) {
+            const int i = (r - nc) / nb, b = (r - nc) % nb, j = c / nv, l = c % nv;
+            v = (i == j) ? A[b * nv + l] : 0.0;
+        }
+        W[e] = v;
+    }
+}
+
+// Column absolute sums of the left half (for ||K||_1) or of the right half.
+__global__ void column_abs_sums(const double* __restrict__ W, int N, int off, double* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double s = 0.0;
+    for (int r = 0; r < N; ++r) s += fabs(W[(size_t)r * 2 * N + off + c]);
+    out[c] = s;
+}
+
+// Gauss-Jordan step k, part 1 (one workgroup): pivot search over rows >= k (largest
+// |W[r][k]|, lowest r on ties), row swap, pivot-row scaling, and a copy of column k
+// (the elimination factors) into f.
+__global__ __launch_bounds__(1024) void gj_pivot(double* __restrict__ W, int N, int k,
+                                                 double* __restrict__ f, int* __restrict__ flag) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    const int tid = threadIdx.x;
+    const size_t ld = 2 * (size_t)N;
+    double best = -1.0;
+    int bi = N;
+    for (int r = k + tid; r < N; r += blockDim.x) {
+        const double v = fabs(W[r * ld + k]);
+        if (v > best) { best = v; bi = r; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double v2 = sv[tid + s];
+            const int i2 = si[tid + s];
+            if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+        }
+        __syncthreads();
+    }
+    __shared__ double s_pv;
+    const int p = si[0];
+    if (tid == 0) {
+        s_pv = (p < N) ? W[p * ld + k] : 0.0;
+        if (!(fabs(s_pv) > 1e-300)) flag[0] = 1;
+    }
+    __syncthreads();                       // the pivot value is read before any row moves
+    const double pv = s_pv;
+    if (p != k && p < N) {
+        for (size_t c = tid; c < ld; c += blockDim.x) {
+            const double t = W[(size_t)k * ld + c];
+            W[(size_t)k * ld + c] = W[(size_t)p * ld + c];
+            W[(size_t)p * ld + c] = t;
+        }
+    }
+    __syncthreads();
+    const double inv = (fabs(pv) > 1e-300) ? 1.0 / pv : 1.0;
+    for (size_t c = tid; c < ld; c += blockDim.x) W[(size_t)k * ld + c] *= inv;
+    __syncthreads();
+    for (int r = tid; r < N; r += blockDim.x) f[r] = (r == k) ? 0.0 : W[(size_t)r * ld + k];
+}
+
+// Gauss-Jordan step k, part 2: W[r][c] -= f[r] W[k][c] for every r != k and c >= k.
+__global__ void gj_eliminate(double* __restrict__ W, int N, int k, const double* __restrict__ f) {
+    const size_t ld = 2 * (size_t)N;
+    const int ncols = 2 * N - k;
+    const size_t total = (size_t)N * ncols;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ncols), c = k + (int)(e % ncols);
+        const double fr = f[r];
+        if (fr != 0.0) W[(size_t)r * ld + c] -= fr * W[(size_t)k * ld + c];
+    }
+}
+
+// Right half of W -> dense N x N inverse.
+__global__ void extract_inverse(const double* __restrict__ W, int N, double* __restrict__ inv) {
+    const size_t total = (size_t)N * N;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / N), c = (int)(e % N);
+        inv[e] = W[(size_t)r * 2 * N + N + c];
+    }
+}
+
+__device__ inline unsigned short bf16_bits_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_bits_to_float(unsigned short h) {
+    return __uint_as_float(((unsigned int)h) << 16);
+}
+
+// GEMM operand: rows 0..M-1 of K^{-1} (all N columns), zero-padded to Mp x ldk.
+// kind 0: fp32; 1: bf16 hi + lo (hi = bf16(x), lo = bf16(fp32(x) - hi)); 2: fp64.
+__global__ void extract_crows(const double* __restrict__ inv, int N, int M, int Mp, int ldk,
+                              int kind, void* __restrict__ hi, void* __restrict__ lo) {
+    const size_t total = (size_t)Mp * ldk;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ldk), c = (int)(e % ldk);
+        const double v = (r < M && c < N) ? inv[(size_t)r * N + c] : 0.0;
+        if (kind == 0) {
+            ((float*)hi)[e] = (float)v;
+        } else if (kind == 1) {
+            const float x = (float)v;
+            const unsigned short h = bf16_bits_rne(x);
+            ((unsigned short*)hi)[e] = h;
+            ((unsigned short*)lo)[e] = bf16_bits_rne(x - bf16_bits_to_float(h));
+        } else {
+            ((double*)hi)[e] = v;
+        }
+    }
+}
+
+static int grid_for(size_t total, int block) {
+    size_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// Inverts the N x N matrix assembled into W (left half) in place; result in `inv`.
+// Returns SINGULAR on a zero pivot; writes ||K||_1 ||K^{-1}||_1 to *cond.
+static mato_status gauss_jordan(double* W, int N, double* inv, double* cond, hipStream_t st) {
+    double *f = nullptr, *cs = nullptr;
+    int* flag = nullptr;
+    MATO_HIP(hipMalloc(&f, sizeof(double) * N));
+    MATO_HIP(hipMalloc(&cs, sizeof(double) * N));
+    MATO_HIP(hipMalloc(&flag, sizeof(int)));
+    MATO_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    std::vector<double> h(N);
+    column_abs_sums<<<(N + 255) / 256, 256, 0, st>>>(W, N, 0, cs);
+    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    MATO_HIP(hipStreamSynchronize(st));
+    double norm1 = 0.0;
+    for (double v : h) norm1 = std::max(norm1, v);
+    for (int k = 0; k < N; ++k) {
+        gj_pivot<<<1, 1024, 0, st>>>(W, N, k, f, flag);
+        const size_t work = (size_t)N * (2 * N - k);
+        gj_eliminate<<<grid_for(work, 256), 256, 0, st>>>(W, N, k, f);
+    }
+    MATO_HIP(hipGetLastError());
+    column_abs_sums<<<(N + 255) / 256, 256, 0, st>>>(W, N, N, cs);
+    int hflag = 0;
+    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    MATO_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    extract_inverse<<<grid_for((size_t)N * N, 256), 256, 0, st>>>(W, N, inv);
+    MATO_HIP(hipStreamSynchronize(st));
+    dfree(f);
+    dfree(cs);
+    dfree(flag);
+    double ninv = 0.0;
+    for (double v : h) ninv = std::max(ninv, v);
+    *cond = norm1 * ninv;
+    if (hflag || !std::isfinite(*cond) || *cond > 1e14) {
+        set_error("KKT matrix is singular or too ill-conditioned (cond estimate %.3e)", *cond);
+        return MATO_ERR_SINGULAR;
+    }
+    return MATO_OK;
+}
+
+template <typename T>
+static mato_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
+    MATO_HIP(hipMalloc(dst, sizeof(T) * src.size()));
+    MATO_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    *bytes += sizeof(T) * src.size();
+    return MATO_OK;
+}
+
+static mato_status plan_build(mato_plan p) {
+    const int n = p->n, nv = p->nv, nb = p->nb, T = p->T;
+    hipStream_t st = p->stream;
+    bernstein_basis(nv, T, p->t_final, p->P, p->Pd, p->Pdd);
+    gram(p->P, T, nv, p->PtP);
+    gram(p->Pdd, T, nv, p->PddtPdd);
+    p->A.assign((size_t)nb * nv, 0.0);
+    for (int j = 0; j < nv; ++j) {
+        p->A[0 * nv + j] = p->P[j];
+        p->A[1 * nv + j] = p->Pd[j];
+        p->A[2 * nv + j] = p->Pdd[j];
+        p->A[3 * nv + j] = p->P[(size_t)(T - 1) * nv + j];
+        p->A[4 * nv + j] = p->Pd[(size_t)(T - 1) * nv + j];
+        p->A[5 * nv + j] = p->Pdd[(size_t)(T - 1) * nv + j];
+    }
+    MATO_TRY(upload(&p->dP, p->P, &p->bytes));
+    MATO_TRY(upload(&p->dPdd, p->Pdd, &p->bytes));
+    MATO_TRY(upload(&p->dPtP, p->PtP, &p->bytes));
+    MATO_TRY(upload(&p->dPddtPdd, p->PddtPdd, &p->bytes));
+    MATO_TRY(upload(&p->dA, p->A, &p->bytes));
+
+    // boundary-only minimum-acceleration KKT (initialisation): [[Pdd^T Pdd, A^T], [A, 0]]
+    {
+        const int N0 = nv + nb;
+        std::vector<double> zeros(nv * nv, 0.0);
+        double *W0 = nullptr, *inv0 = nullptr, *dzero = nullptr;
+        MATO_HIP(hipMalloc(&W0, sizeof(double) * N0 * 2 * N0));
+        MATO_HIP(hipMalloc(&inv0, sizeof(double) * N0 * N0));
+        MATO_HIP(hipMalloc(&dzero, sizeof(double) * nv * nv));
+        MATO_HIP(hipMemcpy(dzero, zeros.data(), sizeof(double) * nv * nv, hipMemcpyHostToDevice));
+        // n = 1, rho = 0: H = Pdd^T Pdd
+        assemble_kkt<<<grid_for((size_t)N0 * 2 * N0, 256), 256, 0, st>>>(W0, 1, nv, nb, 0.0, dzero,
+                                                                         p->dPddtPdd, p->dA);
+        double c0 = 0.0;
+        mato_status s = gauss_jordan(W0, N0, inv0, &c0, st);
+        if (s == MATO_OK) {
+            std::vector<double> h((size_t)N0 * N0);
+            MATO_HIP(hipMemcpy(h.data(), inv0, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+            p->K0inv_c.assign((size_t)nv * nb, 0.0);
+            for (int r = 0; r < nv; ++r)
+                for (int b = 0; b < nb; ++b) p->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
+        }
+        dfree(W0);
+        dfree(inv0);
+        dfree(dzero);
+        if (s != MATO_OK) return s;
+        MATO_TRY(upload(&p->dK0c, p->K0inv_c, &p->bytes));
+    }
+
+    // full KKT matrix of eq. (kkt_step_x) and its inverse
+    const int N = n * (nv + nb), M = n * nv;
+    double* W = nullptr;
+    MATO_HIP(hipMalloc(&W, sizeof(double) * (size_t)N * 2 * N));
+    MATO_HIP(hipMalloc(&p->dKinv, sizeof(double) * (size_t)N * N));
+    p->bytes += sizeof(double) * (size_t)N * N;
+    assemble_kkt<<<grid_for((size_t)N * 2 * N, 256), 256, 0, st>>>(W, n, nv, nb, p->rho, p->dPtP,
+                                                                   p->dPddtPdd, p->dA);
+    mato_status s = gauss_jordan(W, N, p->dKinv, &p->cond, st);
+    dfree(W);
+    if (s != MATO_OK) return s;
+
+    // GEMM operand: c-rows [K11^{-1} | K12^{-1}]
+    const int Mp = round_up(M, 64);
+    p->ldk = round_up(N, 32);
+    const size_t elems = (size_t)Mp * p->ldk;
+    int kind = 0;
+    size_t esz = sizeof(float);
+    if (p->precision == MATO_BF16_REFINED) { kind = 1; esz = 2; }
+    if (p->precision == MATO_FP64) { kind = 2; esz = sizeof(double); }
+    MATO_HIP(hipMalloc(&p->dAhi, esz * elems));
+    p->bytes += esz * elems;
+    if (kind == 1) {
+        MATO_HIP(hipMalloc(&p->dAlo, esz * elems));
+        p->bytes += esz * elems;
+    }
+    extract_crows<<<grid_for(elems, 256), 256, 0, st>>>(p->dKinv, N, M, Mp, p->ldk, kind, p->dAhi, p->dAlo);
+    MATO_HIP(hipGetLastError());
+    MATO_HIP(hipStreamSynchronize(st));
+    return MATO_OK;
+}
+
+}  // namespace mato
+
+using namespace mato;
+
+extern "C" const char* mato_last_error(void) { return mato::last_error(); }
+extern "C" const char* mato_version(void) { return "mato 0.1 (gfx950)"; }
+
+extern "C" void mato_plan_destroy(mato_plan p) {
+    if (!p) return;
+    dfree(p->dKinv);
+    dfree(p->dP);
+    dfree(p->dPdd);
+    dfree(p->dPtP);
+    dfree(p->dPddtPdd);
+    dfree(p->dA);
+    dfree(p->dK0c);
+    dfree(p->dAhi);
+    dfree(p->dAlo);
+    delete p;
+}
+
+extern "C" mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis, double a,
+                                        double b, double rho, int32_t precision, void* hip_stream,
+                                        mato_plan* out) {
+    if (!out || !basis) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (basis->kind != MATO_BASIS_BERNSTEIN) { set_error("unknown basis kind %d", basis->kind); return MATO_ERR_INVALID_ARG; }
+    if (basis->n_coef < 6 || basis->n_coef > kMaxCoef) { set_error("n_coef %d outside 6..%d", basis->n_coef, kMaxCoef); return MATO_ERR_INVALID_ARG; }
+    if (n < 2) { set_error("n = %d < 2", n); return MATO_ERR_INVALID_ARG; }
+    if (n > MATO_MAX_AGENTS) { set_error("n = %d > %d", n, MATO_MAX_AGENTS); return MATO_ERR_UNSUPPORTED; }
+    if (T < basis->n_coef) { set_error("T = %d < n_coef", T); return MATO_ERR_INVALID_ARG; }
+    if (!(a > 0) || !(b > 0) || !(rho > 0) || !(basis->t_final > 0) || !std::isfinite(a) ||
+        !std::isfinite(b) || !std::isfinite(rho) || !std::isfinite(basis->t_final)) {
+        set_error("a, b, rho and t_final must be finite and > 0");
+        return MATO_ERR_INVALID_ARG;
+    }
+    if (precision != MATO_FP64 && precision != MATO_FP32 && precision != MATO_BF16_REFINED) {
+        set_error("unknown precision %d", precision);
+        return MATO_ERR_INVALID_ARG;
+    }
+    mato_plan p = new mato_plan_s();
+    p->n = n; p->T = T; p->nv = basis->n_coef; p->nb = kNb; p->precision = precision;
+    p->t_final = basis->t_final; p->a = a; p->b = b; p->rho = rho; p->cond = 0.0;
+    p->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("no HIP device");
+        delete p;
+        return MATO_ERR_HIP;
+    }
+    mato_status s = plan_build(p);
+    if (s != MATO_OK) {
+        mato_plan_destroy(p);
+        return s;
+    }
+    *out = p;
+    return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_info(mato_plan p, int32_t* n, int32_t* T, int32_t* n_coef,
+                                      int32_t* precision, double* cond) {
+    if (!p) { set_error("null plan"); return MATO_ERR_INVALID_ARG; }
+    if (n) *n = p->n;
+    if (T) *T = p->T;
+    if (n_coef) *n_coef = p->nv;
+    if (precision) *precision = p->precision;
+    if (cond) *cond = p->cond;
+    return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_inverse(mato_plan p, double* kinv) {
+    if (!p || !kinv) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    const size_t N = (size_t)p->n * (p->nv + p->nb);
+    MATO_HIP(hipMemcpyAsync(kinv, p->dKinv, sizeof(double) * N * N, hipMemcpyDefault, p->stream));
+    MATO_HIP(hipStreamSynchronize(p->stream));
+    return MATO_OK;
+}

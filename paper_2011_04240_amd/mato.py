@@ -1,0 +1,362 @@
+"""ctypes binding of libmato (C ABI in include/mato.h).
+
+Argument marshalling only: every step of the iteration runs in the HIP kernels
+of libmato.so.  The functions below carry the C names; ``Plan`` and ``Batch``
+are thin owners of the handles.  Arrays may be NumPy arrays (host) or torch
+tensors (host or device); they are passed by pointer.  The library must have
+been built (``python -m paper_2011_04240_amd.build``): loading fails loudly
+otherwise, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmato.so")
+
+MATO_OK = 0
+MATO_ERR_INVALID_ARG = -1
+MATO_ERR_OUT_OF_MEMORY = -2
+MATO_ERR_SINGULAR = -3
+MATO_ERR_NONFINITE = -4
+MATO_ERR_HIP = -5
+MATO_ERR_UNSUPPORTED = -6
+MATO_ERR_NOT_FOUND = -7
+MATO_WARN_NOT_CONVERGED = 1
+MATO_MAX_AGENTS = 160
+
+MATO_FP64, MATO_FP32, MATO_BF16_REFINED = 0, 1, 2
+PRECISIONS = {"fp64": MATO_FP64, "fp32": MATO_FP32, "bf16": MATO_BF16_REFINED}
+
+
+class MatoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("mato status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_coef", ctypes.c_int32), ("t_final", ctypes.c_double)]
+
+
+_lib = None
+_vp, _i32, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+_pi32, _pf64, _pvp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mato_last_error": (ctypes.c_char_p, []),
+    "mato_version": (ctypes.c_char_p, []),
+    "mato_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _f64, _i32, _vp, _pvp]),
+    "mato_plan_destroy": (None, [_vp]),
+    "mato_plan_info": (_i32, [_vp, _pi32, _pi32, _pi32, _pi32, _pf64]),
+    "mato_plan_inverse": (_i32, [_vp, _vp]),
+    "mato_batch_create": (_i32, [_i32, _pvp, _vp, _vp, _vp, _pvp]),
+    "mato_batch_destroy": (None, [_vp]),
+    "mato_batch_step": (_i32, [_vp, _i32, _f64, _i32]),
+    "mato_batch_run": (_i32, [_vp, _i32, _f64, _i32]),
+    "mato_batch_sync": (_i32, [_vp]),
+    "mato_batch_status": (_i32, [_vp, _i32, _pi32, _pi32]),
+    "mato_batch_coeffs": (_i32, [_vp, _i32, _vp]),
+    "mato_batch_residuals": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _pi32]),
+    "mato_batch_debug": (_i32, [_vp, _i32]),
+    "mato_batch_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "mato_batch_set_state": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "mato_batch_linear_term": (_i32, [_vp, _i32, _vp]),
+    "mato_batch_set_tiles": (_i32, [_vp, _i32, _i32]),
+    "mato_batch_get_tiles": (_i32, [_vp, _pi32, _pi32]),
+    "mato_batch_autotune": (_i32, [_vp, _pi32, _pi32]),
+    "mato_batch_timing": (_i32, [_vp, _i32]),
+    "mato_batch_last_times": (_i32, [_vp, _pf64, _pf64, _pi32]),
+    "mato_solve_run": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _pvp]),
+    "mato_solve_coeffs": (_i32, [_vp, _vp]),
+    "mato_residuals": (_i32, [_vp, _vp, _vp, _vp, _i32, _pi32]),
+    "mato_solve_destroy": (None, [_vp]),
+}
+
+
+def lib():
+    """Load libmato.so (built in-tree).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmato.so not built at %s; run `python -m paper_2011_04240_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status < 0:
+        raise MatoError(status, lib().mato_last_error().decode())
+    return status
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return ctypes.c_void_p(x.ctypes.data)
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(x.data_ptr())
+    raise TypeError("expected a NumPy array or a torch tensor, got %r" % type(x))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# --------------------------------------------------------- thin C wrappers ---
+def mato_version():
+    return lib().mato_version().decode()
+
+
+def mato_plan_create(n, T, n_coef, t_final, a, b, rho, precision, stream=None):
+    h = ctypes.c_void_p()
+    basis = _Basis(0, n_coef, t_final)
+    _check(lib().mato_plan_create(n, T, ctypes.byref(basis), a, b, rho, precision, _stream_ptr(stream),
+                                  ctypes.byref(h)))
+    return h
+
+
+def mato_plan_destroy(plan):
+    lib().mato_plan_destroy(plan)
+
+
+def mato_plan_info(plan):
+    n, T, nc, pr = _i32(), _i32(), _i32(), _i32()
+    cond = _f64()
+    _check(lib().mato_plan_info(plan, ctypes.byref(n), ctypes.byref(T), ctypes.byref(nc), ctypes.byref(pr),
+                                ctypes.byref(cond)))
+    return n.value, T.value, nc.value, pr.value, cond.value
+
+
+def mato_plan_inverse(plan, out):
+    _check(lib().mato_plan_inverse(plan, _ptr(out)))
+
+
+def mato_batch_create(plans, starts, goals, stream=None):
+    arr = (ctypes.c_void_p * len(plans))(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    h = ctypes.c_void_p()
+    _check(lib().mato_batch_create(len(plans), arr, _ptr(starts), _ptr(goals), _stream_ptr(stream),
+                                   ctypes.byref(h)))
+    return h
+
+
+def mato_batch_destroy(batch):
+    lib().mato_batch_destroy(batch)
+
+
+def mato_batch_step(batch, k, tol=0.0, use_graph=True):
+    return _check(lib().mato_batch_step(batch, k, tol, int(bool(use_graph))))
+
+
+def mato_batch_run(batch, iters, tol=0.0, check_every=10):
+    return _check(lib().mato_batch_run(batch, iters, tol, check_every))
+
+
+def mato_batch_sync(batch):
+    return _check(lib().mato_batch_sync(batch))
+
+
+def mato_batch_status(batch, q):
+    it, conv = _i32(), _i32()
+    _check(lib().mato_batch_status(batch, q, ctypes.byref(it), ctypes.byref(conv)))
+    return it.value, bool(conv.value)
+
+
+def mato_batch_coeffs(batch, q, out):
+    _check(lib().mato_batch_coeffs(batch, q, _ptr(out)))
+
+
+def mato_batch_residuals(batch, q, r_max, r_rms, cost, cap):
+    nw = _i32()
+    _check(lib().mato_batch_residuals(batch, q, _ptr(r_max), _ptr(r_rms), _ptr(cost), cap, ctypes.byref(nw)))
+    return nw.value
+
+
+def mato_batch_debug(batch, enable):
+    _check(lib().mato_batch_debug(batch, int(bool(enable))))
+
+
+def mato_batch_get_state(batch, q, c=None, lam=None, proj=None, d=None, X=None):
+    _check(lib().mato_batch_get_state(batch, q, _ptr(c), _ptr(lam), _ptr(proj), _ptr(d), _ptr(X)))
+
+
+def mato_batch_set_state(batch, q, c, lam, proj):
+    _check(lib().mato_batch_set_state(batch, q, _ptr(c), _ptr(lam), _ptr(proj)))
+
+
+def mato_batch_linear_term(batch, q, out):
+    _check(lib().mato_batch_linear_term(batch, q, _ptr(out)))
+
+
+def mato_batch_set_tiles(batch, items_per_wg, threads):
+    _check(lib().mato_batch_set_tiles(batch, items_per_wg, threads))
+
+
+def mato_batch_get_tiles(batch):
+    a, b = _i32(), _i32()
+    _check(lib().mato_batch_get_tiles(batch, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def mato_batch_autotune(batch):
+    a, b = _i32(), _i32()
+    _check(lib().mato_batch_autotune(batch, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def mato_batch_timing(batch, enable):
+    _check(lib().mato_batch_timing(batch, int(bool(enable))))
+
+
+def mato_batch_last_times(batch):
+    t, p, n = _f64(), _f64(), _i32()
+    _check(lib().mato_batch_last_times(batch, ctypes.byref(t), ctypes.byref(p), ctypes.byref(n)))
+    return t.value, p.value, n.value
+
+
+# ---------------------------------------------------------------- owners ---
+class Plan:
+    """K^{-1} of the x/y/z step for one (n, T, basis, rho); a, b are the spheroid dimensions."""
+
+    def __init__(self, n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", stream=None):
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.n, self.T, self.n_coef = n, T, n_coef
+        self.t_final, self.a, self.b, self.rho = t_final, a, b, rho
+        self.handle = mato_plan_create(n, T, n_coef, t_final, a, b, rho, self.precision, stream)
+
+    @property
+    def scalar(self):
+        return np.float64 if self.precision == MATO_FP64 else np.float32
+
+    def info(self):
+        return mato_plan_info(self.handle)
+
+    def inverse(self):
+        N = self.n * (self.n_coef + 6)
+        out = np.empty((N, N), dtype=np.float64)
+        mato_plan_inverse(self.handle, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mato_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems iterated together; problem q uses plans[q]."""
+
+    def __init__(self, plans, starts_list, goals_list, stream=None):
+        self.plans = list(plans)
+        self.ns = [p.n for p in self.plans]
+        starts = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64).reshape(-1, 3) for s in starts_list]))
+        goals = np.ascontiguousarray(np.concatenate([np.asarray(g, np.float64).reshape(-1, 3) for g in goals_list]))
+        self.handle = mato_batch_create([p.handle for p in self.plans], starts, goals, stream)
+
+    def __len__(self):
+        return len(self.plans)
+
+    def step(self, k, tol=0.0, use_graph=True):
+        return mato_batch_step(self.handle, k, tol, use_graph)
+
+    def run(self, iters, tol=0.0, check_every=10):
+        return mato_batch_run(self.handle, iters, tol, check_every)
+
+    def sync(self):
+        mato_batch_sync(self.handle)
+
+    def status(self, q):
+        return mato_batch_status(self.handle, q)
+
+    def coeffs(self, q):
+        p = self.plans[q]
+        out = np.empty((p.n, 3, p.n_coef), dtype=np.float64)
+        mato_batch_coeffs(self.handle, q, out)
+        return out
+
+    def residuals(self, q, cap=1 << 20):
+        it, _ = self.status(q)
+        m = max(0, min(it, cap))
+        r_max, r_rms, cost = (np.empty(max(m, 1)) for _ in range(3))
+        w = mato_batch_residuals(self.handle, q, r_max, r_rms, cost, m)
+        return r_max[:w], r_rms[:w], cost[:w]
+
+    def debug(self, enable=True):
+        mato_batch_debug(self.handle, enable)
+
+    def get_state(self, q, proj=False, d=False, X=False):
+        p = self.plans[q]
+        np_, S = p.n * (p.n - 1) // 2, p.scalar
+        c = np.empty((p.n, 3, p.n_coef), np.float64)
+        lam = np.empty((np_, p.T, 3), S)
+        pj = np.empty((np_, p.T, 3), S) if proj else None
+        dd = np.empty((np_, p.T), S) if d else None
+        xx = np.empty((p.n, 3, p.T), S) if X else None
+        mato_batch_get_state(self.handle, q, c, lam, pj, dd, xx)
+        out = dict(c=c, lam=lam)
+        if proj:
+            out["proj"] = pj
+        if d:
+            out["d"] = dd
+        if X:
+            out["X"] = xx
+        return out
+
+    def set_state(self, q, c, lam, proj):
+        S = self.plans[q].scalar
+        mato_batch_set_state(self.handle, q, np.ascontiguousarray(c, np.float64),
+                             np.ascontiguousarray(lam, S), np.ascontiguousarray(proj, S))
+
+    def linear_term(self, q):
+        p = self.plans[q]
+        out = np.empty((p.n, 3, p.n_coef), np.float64)
+        mato_batch_linear_term(self.handle, q, out)
+        return out
+
+    def set_tiles(self, items_per_wg, threads):
+        mato_batch_set_tiles(self.handle, items_per_wg, threads)
+
+    def get_tiles(self):
+        return mato_batch_get_tiles(self.handle)
+
+    def autotune(self):
+        return mato_batch_autotune(self.handle)
+
+    def timing(self, enable=True):
+        mato_batch_timing(self.handle, enable)
+
+    def last_times(self):
+        return mato_batch_last_times(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mato_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

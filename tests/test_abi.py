@@ -1,0 +1,64 @@
+"""C ABI surface (no GPU): libmato.so loads, exports every function include/mato.h
+declares, the ctypes binding covers exactly those, and argument validation of
+plan creation answers before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2011_04240_amd import mato
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mato_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mato.lib()
+    declared = _declared()
+    assert len(declared) > 20
+    missing = [n for n in sorted(declared) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert set(mato.SIGNATURES) == _declared()
+
+
+def test_version_string():
+    assert "gfx950" in mato.mato_version()
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(n=1), mato.MATO_ERR_INVALID_ARG),
+    (dict(n=mato.MATO_MAX_AGENTS + 1), mato.MATO_ERR_UNSUPPORTED),
+    (dict(a=0.0), mato.MATO_ERR_INVALID_ARG),
+    (dict(b=-1.0), mato.MATO_ERR_INVALID_ARG),
+    (dict(rho=0.0), mato.MATO_ERR_INVALID_ARG),
+    (dict(t_final=float("nan")), mato.MATO_ERR_INVALID_ARG),
+    (dict(n_coef=5), mato.MATO_ERR_INVALID_ARG),
+    (dict(T=8), mato.MATO_ERR_INVALID_ARG),
+    (dict(precision=7), mato.MATO_ERR_INVALID_ARG),
+])
+def test_plan_argument_validation(args, status):
+    kw = dict(n=4, T=50, n_coef=11, t_final=5.0, a=0.4, b=0.8, rho=1.0, precision=mato.MATO_FP32)
+    kw.update(args)
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_plan_create(**kw)
+    assert e.value.status == status
+
+
+def test_null_handles_are_rejected():
+    L = mato.lib()
+    assert L.mato_batch_step(None, 1, 0.0, 0) == mato.MATO_ERR_INVALID_ARG
+    assert L.mato_plan_info(None, None, None, None, None, None) == mato.MATO_ERR_INVALID_ARG
+    assert L.mato_batch_create(0, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == mato.MATO_ERR_INVALID_ARG
