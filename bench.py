@@ -1,0 +1,175 @@
+"""Benchmark of the alternating-minimisation iteration on one MI355X.
+
+One step = one iteration of Algorithm 1 (inverse product with its FP64
+refinement, fused pairwise stage, linear term) over a batch of B independent
+random-box problems with n = 64 agents and T = 100 instants (seeded synthetic
+start/goal positions: uniform in a 10 x 10 x 5 m box, at least 1 m apart).
+
+Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step),
+the roofline of the pairwise kernel (24 algorithmic bytes per pair-instant:
+the FP32 multipliers read and written), timed with HIP events on the batch's
+stream, and the FP64 oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 24            # FP32 lambda: 12 B read + 12 B written per pair-instant
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pairwise_n64_T100_B1024_counters.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=1024, help="problems per launch")
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--T", type=int, default=100)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2011_04240_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters():
+    """HBM bytes per pairwise launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source (else None)."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    vals = {}
+    for line in open(COUNTERS_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n, T, seconds):
+    """The FP64 oracle on one problem of the same workload, BLAS limited to one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import am
+    from paper_2011_04240_amd import scenarios as sc
+    s, g = sc.random_box(n, seed=0)
+    with threadpool_limits(limits=1):
+        plan = am.make_plan(n, T, 11, 10.0, 0.3, 0.6, 1.0)
+        st = am.initial_state(plan, s, g)
+        st = am.iterate(plan, st)                  # warm-up
+        t0 = time.perf_counter()
+        iters = 0
+        while time.perf_counter() - t0 < seconds:
+            st = am.iterate(plan, st)
+            iters += 1
+        dt = time.perf_counter() - t0
+    upd = n * (n - 1) // 2 * T * iters / dt
+    return {"value": upd, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one n=%d T=%d random-box problem, %d FP64 iterations in %.1f s, BLAS 1 thread"
+                      % (n, T, iters, dt)}
+
+
+def copy_calibration(mib):
+    import torch
+    x = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": mib * (1 << 20), "launches": 3}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the problems are independent and this build "
+              "has no multi-GPU path (see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    import torch
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+
+    n, T, B = args.n, args.T, args.batch
+    npairs = n * (n - 1) // 2
+    torch.cuda.set_device(0)
+    starts, goals = zip(*[sc.random_box(n, seed=q) for q in range(B)])
+    t0 = time.perf_counter()
+    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, args.precision)
+    plan_s = time.perf_counter() - t0
+    batch = mato.Batch([plan] * B, starts, goals)
+    tiles = batch.autotune() if not args.no_autotune else batch.get_tiles()
+    batch.step(args.warmup, use_graph=False)
+    batch.sync()
+    batch.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps, use_graph=False)
+    batch.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms, pw_ms, launches = batch.last_times()
+    updates = npairs * T * B * args.steps
+    value = updates / wall
+    pw_avg_s = pw_ms / max(launches, 1) / 1e3
+    alg_bytes = BYTES_PER_UPDATE * npairs * T * B
+    achieved = alg_bytes / pw_avg_s / 1e9
+    traffic = traffic_from_counters() if (n, T, B) == (64, 100, 1024) else None
+    r_max, _, _ = batch.residuals(0)
+    out = {
+        "metric": "pair-timestep updates/s at n=64,T=100",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "random-box problems, n=%d agents, T=%d instants, %d problems per launch" % (n, T, B),
+                   "n": n, "T": T, "problems": B, "precision": args.precision,
+                   "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]},
+                   "device_ms_per_step": total_ms / args.steps, "plan_s": plan_s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -59,12 +59,17 @@ typedef struct {
     double  t_final;   /* horizon in seconds, > 0                          */
 } mato_basis;
 
-/* Arithmetic of the per-iteration path.  The offline inverse is always FP64.
+/* Arithmetic of the per-iteration path.  The offline inverse, the coefficients, the
+ * linear term g and the refinement residual are always FP64.
  *   MATO_FP64        : every stage in FP64 (reference precision on the GPU).
- *   MATO_FP32        : every stage in FP32; the inverse is rounded to FP32.
- *   MATO_BF16_REFINED: FP32 state; the inverse product runs on BF16 MFMA with FP32
- *                      accumulation over a two-term BF16 split of the inverse and of
- *                      the right-hand side, followed by an FP64 residual correction. */
+ *   MATO_FP32        : pairwise stage and multipliers in FP32; the inverse product
+ *                      runs on FP32 MFMA (FP32 accumulation) followed by one FP64
+ *                      residual correction.
+ *   MATO_BF16_REFINED: as MATO_FP32, but the inverse product runs on BF16 MFMA with
+ *                      FP32 accumulation over two-term BF16 splits of the inverse and of
+ *                      the right-hand side, followed by two FP64 residual corrections.
+ * The number of corrections can be overridden with the MATO_REFINE environment
+ * variable (0..4). */
 typedef enum { MATO_FP64 = 0, MATO_FP32 = 1, MATO_BF16_REFINED = 2 } mato_precision;
 
 typedef struct mato_plan_s*   mato_plan;    /* K^{-1} of eq. (kkt_step_x) for one (n, T, basis, rho) */
@@ -140,12 +145,13 @@ mato_status mato_batch_residuals(mato_batch batch, int32_t q, double* r_max, dou
 
 /* Checkpoint / parity hooks.  The state of problem q between iterations is
  * (c, lambda, d e): multipliers and the projected points of eq. (b_f)
- * (b_fc = d e - lambda / rho).  Buffers are in the batch's precision (float for
- * MATO_FP32 / MATO_BF16_REFINED, double for MATO_FP64): c [n][3][n_coef],
- * lambda and proj [n_pairs][T][3].  get_state's `proj`, `d` and `X` need
- * mato_batch_debug(batch, 1) before the iteration that produced them
- * (d: [n_pairs][T]; X: positions [n][3][T]); any output pointer may be NULL.
- * set_state rebuilds the linear term from (lambda, proj); c is kept for reporting. */
+ * (b_fc = d e - lambda / rho).  c is double [n][3][n_coef]; lambda, proj, d and X
+ * are in the batch's scalar (float for MATO_FP32 / MATO_BF16_REFINED, double for
+ * MATO_FP64): lambda and proj [n_pairs][T][3], d [n_pairs][T], X (positions P c of
+ * the current c) [n][3][T].  get_state's `proj` and `d` need mato_batch_debug(batch, 1)
+ * before the iteration that produced them; any output pointer may be NULL.
+ * set_state rebuilds the linear term from (lambda, proj); c, if given, replaces the
+ * reported coefficients and their positions. */
 mato_status mato_batch_debug(mato_batch batch, int32_t enable);
 mato_status mato_batch_get_state(mato_batch batch, int32_t q, void* c, void* lambda,
                                  void* proj, void* d, void* X);

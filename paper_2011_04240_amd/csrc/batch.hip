@@ -25,15 +25,19 @@
 namespace mato {
 
 template <typename S>
-hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int, size_t, hipStream_t);
+hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int, size_t, int, hipStream_t);
 template <typename S>
 hipError_t set_pairwise_lds_limit(size_t);
 template <typename S>
-hipError_t launch_qbuild(const ProblemDesc<S>*, int, int, hipStream_t);
+hipError_t launch_qbuild(const ProblemDesc<S>*, int, int, int, hipStream_t);
 template <typename S>
 hipError_t launch_residual(const ProblemDesc<S>*, int, hipStream_t);
 template <typename S>
+hipError_t launch_positions(const ProblemDesc<S>*, int, int, int, hipStream_t);
+template <typename S>
 hipError_t launch_init(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
+template <typename S>
+hipError_t launch_ceq(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
 hipError_t launch_gemm(int, const GemmTile*, int, const GemmGroup*, const GemmCol*, int, hipStream_t);
 
 static int device_lds_limit() {
@@ -54,7 +58,7 @@ struct BatchImpl {
     struct Prob {
         mato_plan plan;
         int n, np, T, nv, ldq, ldc;
-        size_t o_lam, o_ssum, o_c, o_q, o_r, o_part, o_hist;
+        size_t o_lam, o_ssum, o_X, o_misc, o_c, o_ceq, o_q, o_r, o_qf, o_rf, o_part, o_hist;
         int nslab = 0;
     };
     int precision = MATO_FP32;
@@ -71,6 +75,7 @@ struct BatchImpl {
     std::vector<ProblemDesc<S>> hdesc;
     ProblemDesc<S>* ddesc = nullptr;
     double** dk0c = nullptr;
+    double** dkinv = nullptr;
 
     std::vector<WorkItem> hitems;
     WorkItem* ditems = nullptr;
@@ -106,6 +111,7 @@ struct BatchImpl {
         dfree(dctrl);
         dfree(ddesc);
         dfree(dk0c);
+        dfree(dkinv);
         dfree(ditems);
         dfree(dgroups);
         dfree(dtiles);
@@ -118,6 +124,14 @@ struct BatchImpl {
     }
 
     int count() const { return (int)probs.size(); }
+
+    // number of basis coefficients shared by every problem (0 if they differ)
+    int common_nv() const {
+        int nv = probs.empty() ? 0 : probs[0].nv;
+        for (const auto& P : probs)
+            if (P.nv != nv) return 0;
+        return nv;
+    }
 
     // ------------------------------------------------------------ layout ---
     mato_status build_items() {
@@ -157,9 +171,14 @@ struct BatchImpl {
         for (auto& P : probs) {
             P.o_lam = off;  off += al(sizeof(S) * (size_t)P.T * 3 * P.np);
             P.o_ssum = off; off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
+            P.o_X = off;    off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
+            P.o_misc = off; off += al(sizeof(double) * 4);
             P.o_c = off;    off += al(sizeof(double) * 3 * (size_t)P.ldc);
+            P.o_ceq = off;  off += al(sizeof(double) * 3 * (size_t)P.ldc);
             P.o_q = off;    off += al(sizeof(double) * 3 * (size_t)P.ldq);
             P.o_r = off;    off += al(sizeof(double) * 3 * (size_t)P.ldq);
+            P.o_qf = off;   off += al(sizeof(float) * 3 * (size_t)P.ldq);
+            P.o_rf = off;   off += al(sizeof(float) * 3 * (size_t)P.ldq);
             P.o_part = off; off += al(part_bytes_for(P));   // at most T slabs
             P.o_hist = off; off += al(sizeof(double) * 3 * kHistCap);
         }
@@ -173,9 +192,14 @@ struct BatchImpl {
         MATO_HIP(hipMalloc(&dctrl, sizeof(int) * 4 * count()));
         MATO_HIP(hipMalloc(&ddesc, sizeof(ProblemDesc<S>) * count()));
         MATO_HIP(hipMalloc(&dk0c, sizeof(double*) * count()));
-        std::vector<double*> k0(count());
-        for (int q = 0; q < count(); ++q) k0[q] = probs[q].plan->dK0c;
+        MATO_HIP(hipMalloc(&dkinv, sizeof(double*) * count()));
+        std::vector<double*> k0(count()), ki(count());
+        for (int q = 0; q < count(); ++q) {
+            k0[q] = probs[q].plan->dK0c;
+            ki[q] = probs[q].plan->dKinv;
+        }
         MATO_HIP(hipMemcpy(dk0c, k0.data(), sizeof(double*) * count(), hipMemcpyHostToDevice));
+        MATO_HIP(hipMemcpy(dkinv, ki.data(), sizeof(double*) * count(), hipMemcpyHostToDevice));
         return MATO_OK;
     }
 
@@ -195,11 +219,17 @@ struct BatchImpl {
             D.srho = (S)pl->rho;
             D.sirho = (S)(1.0 / pl->rho);
             D.P = pl->dP; D.Pdd = pl->dPdd; D.PtP = pl->dPtP; D.PddtPdd = pl->dPddtPdd; D.A = pl->dA;
+            D.pairs = pl->dPairs;
             D.lam = (S*)(arena + P.o_lam);
             D.ssum = (S*)(arena + P.o_ssum);
+            D.X = (S*)(arena + P.o_X);
+            D.misc = (double*)(arena + P.o_misc);
             D.c = (double*)(arena + P.o_c);
+            D.ceq = (double*)(arena + P.o_ceq);
             D.q = (double*)(arena + P.o_q);
             D.r = (double*)(arena + P.o_r);
+            D.qf = (float*)(arena + P.o_qf);
+            D.rf = (float*)(arena + P.o_rf);
             D.part = (double*)(arena + P.o_part);
             D.hist = (double*)(arena + P.o_hist);
             D.ctrl = dctrl + 4 * q;
@@ -211,7 +241,6 @@ struct BatchImpl {
                 const Prob& P = probs[q];
                 hdesc[q].dbg_proj = dbg + off; off += (size_t)P.T * 3 * P.np;
                 hdesc[q].dbg_d = dbg + off;    off += (size_t)P.T * P.np;
-                hdesc[q].dbg_X = dbg + off;    off += (size_t)P.T * 3 * P.n;
             }
         }
     }
@@ -253,7 +282,7 @@ struct BatchImpl {
             G.Ahi = pl->dAhi;
             G.Alo = pl->dAlo;
             G.M = pl->n * pl->nv;
-            G.K = pl->n * (pl->nv + pl->nb);
+            G.K = pl->n * pl->nv;
             G.ldk = pl->ldk;
             G.ncols = 3 * (int)mem.size();
             G.first_col = (int)colq.size();
@@ -262,8 +291,11 @@ struct BatchImpl {
                     const Prob& P = probs[q];
                     GemmCol cq, cr;
                     cq.c = cr.c = (double*)(arena + P.o_c) + (size_t)a * P.ldc;
+                    cq.ceq = cr.ceq = (const double*)(arena + P.o_ceq) + (size_t)a * P.ldc;
                     cq.b = (const double*)(arena + P.o_q) + (size_t)a * P.ldq;
                     cr.b = (const double*)(arena + P.o_r) + (size_t)a * P.ldq;
+                    cq.bf = (const float*)(arena + P.o_qf) + (size_t)a * P.ldq;
+                    cr.bf = (const float*)(arena + P.o_rf) + (size_t)a * P.ldq;
                     cq.ctrl = cr.ctrl = dctrl + 4 * q;
                     colq.push_back(cq);
                     colr.push_back(cr);
@@ -300,12 +332,16 @@ struct BatchImpl {
                     b[0] = starts[(size_t)(agent_off[q] + i) * 3 + a];
                     b[3] = goals[(size_t)(agent_off[q] + i) * 3 + a];
                 }
+            std::vector<float> hf(hq.begin(), hq.end());
             MATO_HIP(hipMemcpyAsync(arena + P.o_q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, stream));
+            MATO_HIP(hipMemcpyAsync(arena + P.o_qf, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice, stream));
             MATO_HIP(hipStreamSynchronize(stream));
         }
         MATO_HIP(launch_init<S>(ddesc, dk0c, count(), stream));
-        MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, stream));
-        MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, stream));
+        MATO_HIP(launch_ceq<S>(ddesc, dkinv, count(), stream));
+        MATO_HIP(launch_positions<S>(ddesc, count(), kModeInit, common_nv(), stream));
+        MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, common_nv(), stream));
+        MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, common_nv(), stream));
         return MATO_OK;
     }
 
@@ -318,6 +354,8 @@ struct BatchImpl {
             e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
             if (e != hipSuccess) return e;
         }
+        e = launch_positions<S>(ddesc, count(), kModeIter, common_nv(), st);
+        if (e != hipSuccess) return e;
         if (events) {
             while ((int)pw_events.size() < pw_used + 2) {
                 hipEvent_t ev;
@@ -328,14 +366,14 @@ struct BatchImpl {
             e = hipEventRecord(pw_events[pw_used], st);
             if (e != hipSuccess) return e;
         }
-        e = launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, st);
+        e = launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, common_nv(), st);
         if (e != hipSuccess) return e;
         if (events) {
             e = hipEventRecord(pw_events[pw_used + 1], st);
             if (e != hipSuccess) return e;
             pw_used += 2;
         }
-        return launch_qbuild<S>(ddesc, count(), kModeIter, st);
+        return launch_qbuild<S>(ddesc, count(), kModeIter, common_nv(), st);
     }
 
     void drop_graphs() {
@@ -480,11 +518,11 @@ struct BatchImpl {
         for (int ipw : ipws)
             for (int thr : thrs) {
                 if (set_tiles(ipw, thr) != MATO_OK) continue;
-                MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, stream));
+                MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, common_nv(), stream));
                 MATO_HIP(hipEventRecord(e0, stream));
                 const int reps = 5;
                 for (int r = 0; r < reps; ++r)
-                    MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, stream));
+                    MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, common_nv(), stream));
                 MATO_HIP(hipEventRecord(e1, stream));
                 MATO_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -509,7 +547,7 @@ struct BatchImpl {
         MATO_HIP(hipStreamSynchronize(stream));
         if (on && !dbg) {
             size_t elems = 0;
-            for (auto& P : probs) elems += (size_t)P.T * (4 * (size_t)P.np + 3 * P.n);
+            for (auto& P : probs) elems += (size_t)P.T * 4 * (size_t)P.np;
             dbg_bytes = sizeof(S) * std::max<size_t>(elems, 1);
             MATO_HIP(hipMalloc(&dbg, dbg_bytes));
             MATO_HIP(hipMemset(dbg, 0, dbg_bytes));
@@ -536,7 +574,7 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
         P.np = P.n * (P.n - 1) / 2;
         P.T = plans[q]->T;
         P.nv = plans[q]->nv;
-        P.ldq = plans[q]->ldk;
+        P.ldq = round_up(P.n * (P.nv + kNb), 32);   // >= the operand stride ldk = round_up(11n, 32)
         P.ldc = P.n * P.nv;
         B->probs.push_back(P);
         B->agent_off.push_back(agents);
@@ -728,7 +766,7 @@ static mato_status get_state_impl(BatchImpl<S>* B, int q, void* c, void* lambda,
     };
     if (lambda) MATO_TRY(pairwise_out((const S*)(B->arena + P.o_lam), lambda));
     const ProblemDesc<S>& D = B->hdesc[q];
-    if ((proj || d || X) && !D.dbg_proj) { set_error("enable mato_batch_debug before reading proj, d or X"); return MATO_ERR_INVALID_ARG; }
+    if ((proj || d) && !D.dbg_proj) { set_error("enable mato_batch_debug before reading proj or d"); return MATO_ERR_INVALID_ARG; }
     if (proj) MATO_TRY(pairwise_out(D.dbg_proj, proj));
     if (d) {
         std::vector<S> h(npt), o(npt);
@@ -740,7 +778,7 @@ static mato_status get_state_impl(BatchImpl<S>* B, int q, void* c, void* lambda,
     if (X) {
         const size_t nx = (size_t)P.n * 3 * P.T;
         std::vector<S> h(nx), o(nx);
-        MATO_HIP(hipMemcpy(h.data(), D.dbg_X, sizeof(S) * nx, hipMemcpyDeviceToHost));
+        MATO_HIP(hipMemcpy(h.data(), D.X, sizeof(S) * nx, hipMemcpyDeviceToHost));
         for (int t = 0; t < P.T; ++t)
             for (int a = 0; a < 3; ++a)
                 for (int i = 0; i < P.n; ++i) o[((size_t)i * 3 + a) * P.T + t] = h[((size_t)t * 3 + a) * P.n + i];
@@ -803,8 +841,9 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     ctrl[2] = 0;
     ctrl[3] = 1;
     MATO_HIP(hipMemcpy(B->dctrl + 4 * q, ctrl, sizeof(ctrl), hipMemcpyHostToDevice));
-    MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->stream));
-    MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->stream));
+    MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->common_nv(), B->stream));
+    MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
+    if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(hipStreamSynchronize(B->stream));
     dfree(dproj);
     dfree(ditems);

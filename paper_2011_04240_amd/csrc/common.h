@@ -68,19 +68,24 @@ struct ProblemDesc {
     const double* PtP;          // [nv][nv]
     const double* PddtPdd;      // [nv][nv]
     const double* A;            // [6][nv] boundary rows
+    const unsigned* pairs;      // [np] pair p -> i | j << 16
     S* lam;                     // [T][3][np] multipliers
     S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
+    S* X;                       // [T][3][n]  positions P c of the current coefficients
+    double* misc;               // [4]        [0] smoothness cost of the current coefficients
     double* c;                  // [3][ldc]   coefficients (agent-major per axis)
+    double* ceq;                // [3][ldc]   c_eq = K12^{-1} b_eq (boundary part of the product)
     double* q;                  // [3][ldq]   [rho A_fc^T b_fc ; b_eq]  (eq. kkt_step_x)
-    double* r;                  // [3][ldq]   refinement residual [g - H c ; b_eq - A c]
-    double* part;               // [nslab][4] residual partials: max|f|^2, sum|f|^2, cost
+    double* r;                  // [3][ldq]   refinement residual g - H c (first 11n entries)
+    float* qf;                  // [3][ldq]   q rounded to FP32 (inverse-product operand)
+    float* rf;                  // [3][ldq]   r rounded to FP32
+    double* part;               // [nslab][4] residual partials: max|f|^2, sum|f|^2
     double* hist;               // [hist_cap][3] r_max, r_rms, cost
     int* ctrl;                  // [0] iterations, [1] converged, [2] non-finite, [3] active
     double tol;                 // convergence threshold on r_max (<= 0: none)
     // optional parity outputs (nullptr = off)
     S* dbg_proj;                // [T][3][np] d e
     S* dbg_d;                   // [T][np]
-    S* dbg_X;                   // [T][3][n]
     const S* proj_in;           // set-state input [T][3][np]
 };
 
@@ -92,17 +97,19 @@ struct GemmTile {               // one 64-row x 64-column output tile of one sam
     int group, m0, col0, pad;
 };
 
-struct GemmGroup {              // problems sharing one plan: C[:, col] (+)= Kc x B[:, col]
-    const void* Ahi;            // [M][ldk] c-rows [K11^{-1} | K12^{-1}] (fp32 / bf16 hi / fp64)
+struct GemmGroup {              // problems sharing one plan: C[:, col] = c_eq + K11^{-1} B[:, col]
+    const void* Ahi;            // [Mp][ldk] K11^{-1} (fp32 / bf16 hi / fp64), zero padded
     const void* Alo;            // bf16 lo (BF16 split only)
-    int M, K, ldk;              // 11n, 17n, padded row stride of A
+    int M, K, ldk;              // 11n, 11n, padded row stride of A (multiple of 32)
     int ncols;                  // 3 x members
     int first_col;              // offset into the column table
 };
 
 struct GemmCol {                // one right-hand side: problem axis
-    const double* b;            // K entries (q or r)
+    const double* b;            // K entries (q or r), FP64
+    const float* bf;            // the same rounded to FP32 (FP32 / BF16 products)
     double* c;                  // M entries
+    const double* ceq;          // M entries, added when not accumulating
     const int* ctrl;            // problem control word (skip when converged / inactive)
 };
 
@@ -123,7 +130,8 @@ struct mato_plan_s {
     double* dPddtPdd = nullptr;
     double* dA = nullptr;        // [6][nv]
     double* dK0c = nullptr;      // [nv][6] c-rows / b_eq-columns of the boundary-only inverse
-    void* dAhi = nullptr;        // GEMM operand, c-rows of K^{-1}: fp32, bf16 hi or fp64
+    unsigned* dPairs = nullptr;  // [n(n-1)/2] pair p -> i | j << 16 in the row order of A_fc
+    void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 hi or fp64
     void* dAlo = nullptr;        // bf16 lo part
     int ldk = 0;                 // padded row stride of the GEMM operand
     size_t bytes = 0;            // device bytes held

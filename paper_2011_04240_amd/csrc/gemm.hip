@@ -1,19 +1,20 @@
 // The x/y/z QP step through the precomputed inverse, eq. (kkt_step_x) and
 // Remarks 1-2: for every right-hand side (problem, axis) of a same-plan group
-//     c (+)= [K11^{-1} | K12^{-1}] [g ; b_eq]           (c-rows of K^{-1} q~),
-// one dense (11n x 17n) x (17n x 3B) product per iteration for B problems.
-// With accumulate = 1 the same product is applied to the FP64 refinement
-// residual [g - H c ; b_eq - A c] and added to c (K11^{-1} A^T = 0, so the
-// boundary multipliers nu are not needed for the correction).
+//     c = c_eq + K11^{-1} g,     c_eq = K12^{-1} b_eq       (c-rows of K^{-1} q~),
+// one dense (11n x 11n) x (11n x 3B) product per iteration for B problems; c_eq
+// is formed once per problem in FP64.  With accumulate = 1 the same product is
+// applied to the FP64 refinement residual g - H c and added to c (K11^{-1} A^T = 0,
+// so the boundary multipliers nu are not needed for the correction).
 //
-// Tiles are 64 rows x 64 right-hand sides; 256 threads = 4 wavefronts, each
-// owning a 32 x 32 quadrant computed as 2 x 2 blocks of 16 x 16 MFMA outputs.
+// Tiles are 64 rows x 64 right-hand sides; in each group of 4 wavefronts a
+// wavefront owns a 32 x 32 quadrant computed as 2 x 2 blocks of 16 x 16 MFMA outputs.
 //   gemm_f32   v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation.
 //   gemm_bf16  v_mfma_f32_16x16x32_bf16 over two-term BF16 splits of both
 //              operands (hi*hi + hi*lo + lo*hi), FP32 accumulation.
 //   gemm_f64   FP64 FMA (the reference-precision path).
-// Right-hand sides are FP64 in memory and rounded on the way into LDS; the
-// product is added to the FP64 coefficients in the epilogue.
+// The MFMA kernels read the FP32 copy of the right-hand sides (the BF16 kernel
+// splits it on the way into LDS); the product is added to the FP64
+// coefficients in the epilogue.
 #include "common.h"
 
 namespace mato {
@@ -31,14 +32,16 @@ __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsign
 
 struct TileCols {
     const double* bptr;
+    const float* bfptr;
     bool active;
 };
 
 __device__ inline TileCols load_col(const GemmGroup& G, const GemmCol* __restrict__ cols, int col) {
-    TileCols r{nullptr, false};
+    TileCols r{nullptr, nullptr, false};
     if (col < G.ncols) {
         const GemmCol cc = cols[G.first_col + col];
         r.bptr = cc.b;
+        r.bfptr = cc.bf;
         r.active = cc.ctrl[3] && !cc.ctrl[1];
     }
     return r;
@@ -50,140 +53,225 @@ __device__ inline void store_out(const GemmGroup& G, const GemmCol* __restrict__
     const GemmCol cc = cols[G.first_col + col];
     if (!cc.ctrl[3] || cc.ctrl[1]) return;
     double* c = cc.c + row;
-    *c = accumulate ? *c + v : v;
+    *c = (accumulate ? *c : cc.ceq[row]) + v;
 }
 
-__global__ __launch_bounds__(256) void gemm_f32(const GemmTile* __restrict__ tiles,
+// Both MFMA kernels use 512 threads: two groups of four wavefronts walk the even and
+// the odd 32-wide K steps of the same 64 x 64 output tile (each group with its own
+// LDS stage), and the two partial tiles are added in a fixed order at the end.
+// In a group, lane `lr` (0..63) of wavefront w loads row m0 + lr of K11^{-1} and
+// right-hand side col0 + lr, k-slice [8w, 8w + 8) of the step; the next step is
+// fetched into registers while the current one is multiplied out of LDS.  Right-hand
+// sides past the group's last column alias column 0 (their results are discarded).
+__device__ inline const float* col_ptr(const GemmGroup& G, const GemmCol* __restrict__ cols, int col,
+                                       bool& active) {
+    const int cidx = col < G.ncols ? col : 0;
+    const GemmCol cc = cols[G.first_col + cidx];
+    active = col < G.ncols && cc.ctrl[3] && !cc.ctrl[1];
+    return cc.bf;
+}
+
+// Epilogue: group 1 hands its partial tile to group 0 through LDS, group 0 adds it
+// and writes c (+)= result for the active right-hand sides.
+__device__ inline void finish_tile(const GemmTile& t, const GemmGroup& G, const GemmCol* __restrict__ cols,
+                                   floatx4 (&acc)[2][2], float* red, int grp, int wq, int lane, int accumulate) {
+    const int wm = wq >> 1, wn = wq & 1;
+    __syncthreads();
+    if (grp == 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[((wq * 4 + i * 2 + j) * 4 + r) * 64 + lane] = acc[i][j][r];
+    }
+    __syncthreads();
+    if (grp != 0) return;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = t.col0 + wn * 32 + j * 16 + (lane & 15);
+        if (col >= G.ncols) continue;
+        const GemmCol cc = cols[G.first_col + col];
+        if (!cc.ctrl[3] || cc.ctrl[1]) continue;
+        double old[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = t.m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                old[i][r] = row < G.M ? (accumulate ? cc.c[row] : cc.ceq[row]) : 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = t.m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const float v = acc[i][j][r] + red[((wq * 4 + i * 2 + j) * 4 + r) * 64 + lane];
+                if (row < G.M) cc.c[row] = old[i][r] + (double)v;
+            }
+    }
+}
+
+__global__ __launch_bounds__(512) void gemm_f32(const GemmTile* __restrict__ tiles,
                                                 const GemmGroup* __restrict__ groups,
                                                 const GemmCol* __restrict__ cols, int accumulate) {
     const GemmTile t = tiles[blockIdx.x];
     const GemmGroup G = groups[t.group];
-    __shared__ float As[32][68];   // [k][m]
-    __shared__ float Bs[32][68];   // [k][rhs]
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int lr = tid >> 2, kc = (tid & 3) * 8;     // loader: row / rhs lr, k-chunk kc
-    const TileCols bc = load_col(G, cols, t.col0 + lr);
-    if (!__syncthreads_or(bc.active)) return;        // every right-hand side converged
-    const float* arow = (const float*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kc;
+    constexpr int LD = 80;                      // row stride: conflict-free MFMA operand reads
+    __shared__ float smem[2 * 2 * 32 * LD];     // per group: A [k][m], B [k][rhs]
+    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
+    const int lane = gt & 63, wq = gt >> 6;
+    const int wm = wq >> 1, wn = wq & 1;
+    const int lr = gt & 63, kq = (gt >> 6) * 8;
+    float* As = smem + grp * 2 * 32 * LD;
+    float* Bs = As + 32 * LD;
+    bool act;
+    const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
+    if (!__syncthreads_or(act)) return;         // every right-hand side converged
+    const float* arow = (const float*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const int nk = G.ldk / 32;
+    const int nsteps = (nk + 1) / 2;            // steps per group (group 1 may idle on the last)
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < G.ldk; k0 += 32) {
-        const float4 a0 = *(const float4*)(arow + k0);
-        const float4 a1 = *(const float4*)(arow + k0 + 4);
-        double bv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = bc.active ? bc.bptr[k0 + kc + e] : 0.0;
-        As[kc + 0][lr] = a0.x; As[kc + 1][lr] = a0.y; As[kc + 2][lr] = a0.z; As[kc + 3][lr] = a0.w;
-        As[kc + 4][lr] = a1.x; As[kc + 5][lr] = a1.y; As[kc + 6][lr] = a1.z; As[kc + 7][lr] = a1.w;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[kc + e][lr] = (float)bv[e];
+    float4 ra0, ra1, rb0, rb1;
+    auto fetch = [&](int s) {
+        const int k0 = (2 * s + grp) * 32;
+        if (k0 < G.ldk) {
+            ra0 = *(const float4*)(arow + k0);
+            ra1 = *(const float4*)(arow + k0 + 4);
+            rb0 = *(const float4*)(brow + k0);
+            rb1 = *(const float4*)(brow + k0 + 4);
+        }
+    };
+    fetch(0);
+    for (int s = 0; s < nsteps; ++s) {
+        const bool valid = (2 * s + grp) < nk;
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 32; kk += 4) {
-            const int kr = kk + (lane >> 4);
-            float af[2], bf[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        if (valid) {
+            As[(kq + 0) * LD + lr] = ra0.x; As[(kq + 1) * LD + lr] = ra0.y;
+            As[(kq + 2) * LD + lr] = ra0.z; As[(kq + 3) * LD + lr] = ra0.w;
+            As[(kq + 4) * LD + lr] = ra1.x; As[(kq + 5) * LD + lr] = ra1.y;
+            As[(kq + 6) * LD + lr] = ra1.z; As[(kq + 7) * LD + lr] = ra1.w;
+            Bs[(kq + 0) * LD + lr] = rb0.x; Bs[(kq + 1) * LD + lr] = rb0.y;
+            Bs[(kq + 2) * LD + lr] = rb0.z; Bs[(kq + 3) * LD + lr] = rb0.w;
+            Bs[(kq + 4) * LD + lr] = rb1.x; Bs[(kq + 5) * LD + lr] = rb1.y;
+            Bs[(kq + 6) * LD + lr] = rb1.z; Bs[(kq + 7) * LD + lr] = rb1.w;
         }
         __syncthreads();
-    }
+        if (s + 1 < nsteps) fetch(s + 1);
+        if (valid) {
+            float af[8][2], bf[8][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+            for (int kk = 0; kk < 8; ++kk) {
+                const int kr = (4 * kk + (lane >> 4)) * LD;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i) af[kk][i] = As[kr + wm * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = t.m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                const int col = t.col0 + wn * 32 + j * 16 + (lane & 15);
-                store_out(G, cols, row, col, (double)acc[i][j][r], accumulate);
+                for (int j = 0; j < 2; ++j) bf[kk][j] = Bs[kr + wn * 32 + j * 16 + (lane & 15)];
             }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
+        }
+    }
+    finish_tile(t, G, cols, acc, smem, grp, wq, lane, accumulate);
 }
 
-__global__ __launch_bounds__(256) void gemm_bf16(const GemmTile* __restrict__ tiles,
+__device__ inline void split8(const float4& x0, const float4& x1, ushortx8& hi, ushortx8& lo) {
+    const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const unsigned short h = f2bf_rne(v[e]);
+        hi[e] = h;
+        lo[e] = f2bf_rne(v[e] - bf2f(h));
+    }
+}
+
+__global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ tiles,
                                                  const GemmGroup* __restrict__ groups,
                                                  const GemmCol* __restrict__ cols, int accumulate) {
     const GemmTile t = tiles[blockIdx.x];
     const GemmGroup G = groups[t.group];
-    __shared__ __align__(16) unsigned short Ah[64][40], Al[64][40];   // [m][k]
-    __shared__ __align__(16) unsigned short Bh[64][40], Bl[64][40];   // [rhs][k]
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int lr = tid >> 2, kc = (tid & 3) * 8;
-    const TileCols bc = load_col(G, cols, t.col0 + lr);
-    if (!__syncthreads_or(bc.active)) return;
-    const unsigned short* ahi = (const unsigned short*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kc;
-    const unsigned short* alo = (const unsigned short*)G.Alo + (size_t)(t.m0 + lr) * G.ldk + kc;
+    constexpr int LDH = 40;                                   // [row][k] stride in bf16 elements
+    __shared__ __align__(16) unsigned short smem[2 * 4 * 64 * LDH];
+    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
+    const int lane = gt & 63, wq = gt >> 6;
+    const int wm = wq >> 1, wn = wq & 1;
+    const int lr = gt & 63, kq = (gt >> 6) * 8;
+    unsigned short* Ah = smem + grp * 4 * 64 * LDH;
+    unsigned short* Al = Ah + 64 * LDH;
+    unsigned short* Bh = Al + 64 * LDH;
+    unsigned short* Bl = Bh + 64 * LDH;
+    bool act;
+    const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
+    if (!__syncthreads_or(act)) return;
+    const unsigned short* ahi = (const unsigned short*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const unsigned short* alo = (const unsigned short*)G.Alo + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const int nk = G.ldk / 32;
+    const int nsteps = (nk + 1) / 2;
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < G.ldk; k0 += 32) {
-        const ushortx8 vh = *(const ushortx8*)(ahi + k0);
-        const ushortx8 vl = *(const ushortx8*)(alo + k0);
-        double bv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = bc.active ? bc.bptr[k0 + kc + e] : 0.0;
-        *(ushortx8*)&Ah[lr][kc] = vh;
-        *(ushortx8*)&Al[lr][kc] = vl;
+    ushortx8 vh, vl;
+    float4 rb0, rb1;
+    auto fetch = [&](int s) {
+        const int k0 = (2 * s + grp) * 32;
+        if (k0 < G.ldk) {
+            vh = *(const ushortx8*)(ahi + k0);
+            vl = *(const ushortx8*)(alo + k0);
+            rb0 = *(const float4*)(brow + k0);
+            rb1 = *(const float4*)(brow + k0 + 4);
+        }
+    };
+    fetch(0);
+    for (int s = 0; s < nsteps; ++s) {
+        const bool valid = (2 * s + grp) < nk;
         ushortx8 bh, bl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float x = (float)bv[e];
-            const unsigned short h = f2bf_rne(x);
-            bh[e] = h;
-            bl[e] = f2bf_rne(x - bf2f(h));
-        }
-        *(ushortx8*)&Bh[lr][kc] = bh;
-        *(ushortx8*)&Bl[lr][kc] = bl;
+        if (valid) split8(rb0, rb1, bh, bl);
         __syncthreads();
-        const int kq = 8 * (lane >> 4);
-        bf16x8 a_h[2], a_l[2], b_h[2], b_l[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int m = wm * 32 + i * 16 + (lane & 15);
-            a_h[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Ah[m][kq]);
-            a_l[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Al[m][kq]);
+        if (valid) {
+            *(ushortx8*)&Ah[lr * LDH + kq] = vh;
+            *(ushortx8*)&Al[lr * LDH + kq] = vl;
+            *(ushortx8*)&Bh[lr * LDH + kq] = bh;
+            *(ushortx8*)&Bl[lr * LDH + kq] = bl;
         }
+        __syncthreads();
+        if (s + 1 < nsteps) fetch(s + 1);
+        if (valid) {
+            const int kb = 8 * (lane >> 4);
+            bf16x8 a_h[2], a_l[2], b_h[2], b_l[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int c = wn * 32 + j * 16 + (lane & 15);
-            b_h[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bh[c][kq]);
-            b_l[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bl[c][kq]);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i) {
+                const int m = wm * 32 + i * 16 + (lane & 15);
+                a_h[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Ah[m * LDH + kb]);
+                a_l[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Al[m * LDH + kb]);
+            }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_h[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_l[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[i], b_h[j], acc[i][j], 0, 0, 0);
+                const int c = wn * 32 + j * 16 + (lane & 15);
+                b_h[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bh[c * LDH + kb]);
+                b_l[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bl[c * LDH + kb]);
             }
-        __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_h[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_l[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[i], b_h[j], acc[i][j], 0, 0, 0);
+                }
+        }
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = t.m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                const int col = t.col0 + wn * 32 + j * 16 + (lane & 15);
-                store_out(G, cols, row, col, (double)acc[i][j][r], accumulate);
-            }
+    finish_tile(t, G, cols, acc, reinterpret_cast<float*>(smem), grp, wq, lane, accumulate);
 }
 
 __global__ __launch_bounds__(256) void gemm_f64(const GemmTile* __restrict__ tiles,
@@ -231,9 +319,9 @@ hipError_t launch_gemm(int precision, const GemmTile* tiles, int ntiles, const G
                        const GemmCol* cols, int accumulate, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (precision == MATO_FP32)
-        gemm_f32<<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
+        gemm_f32<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
     else if (precision == MATO_BF16_REFINED)
-        gemm_bf16<<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
+        gemm_bf16<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
     else
         gemm_f64<<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
     return hipGetLastError();

@@ -1,17 +1,18 @@
 // Per-iteration kernels of Algorithm 1 other than the inverse product.
 //
-//   pairwise_kernel  positions X = P c (eq. (param)) for a block of instants, then for
-//                    every pair p = (i, j), i < j, at those instants: the difference
+//   pairwise_kernel  for a block of instants and every pair p = (i, j), i < j: the difference
 //                    delta = X_i - X_j, the alpha/beta projection of eq.
 //                    (sphere_project), the clipped d step of eq. (step_d), the
 //                    multiplier update of eq. (lag_update), b_fc of eq. (b_f) for the
 //                    next x/y/z step, and the per-agent sums
 //                    S_i(t) = sum_{j>i} b_ij(t) - sum_{j<i} b_ji(t)
 //                    that A_fc^T b reduces to before the factor P^T.
+//   positions_kernel X = P c at every instant and the smoothness cost, once per problem.
 //   qbuild_kernel    g = rho A_fc^T b_fc = rho P^T S_i (FP64), plus the iteration's
 //                    residual record and the convergence test.
-//   residual_kernel  FP64 refinement residual [g - H c ; b_eq - A c] of eq. (kkt_step_x),
-//                    with H c = (I (x) Pdd^T Pdd) c + rho ((n I - 1 1^T) (x) P^T P) c.
+//   residual_kernel  FP64 refinement residual g - H c of eq. (kkt_step_x), with
+//                    H c = (I (x) Pdd^T Pdd) c + rho ((n I - 1 1^T) (x) P^T P) c.
+//   ceq_kernel       c_eq = K12^{-1} b_eq, the boundary part of the inverse product.
 //   init_kernel      boundary-only minimum-acceleration coefficients (initialisation).
 //
 // The alpha/beta/d step is evaluated without trigonometry.  With the scaled
@@ -21,28 +22,23 @@
 //     d e = w delta with w = d / s = max(1/s, 1 + delta^T lambda / (rho ||delta||^2)),
 //     f_c = delta - d e.
 // delta = 0 takes alpha = beta = 0, i.e. e = (0, 0, l_z).
+//
+// Descriptor fields are read into registers once per workgroup and device
+// pointers are used in the global address space, so that stores cannot force
+// the descriptors to be re-read and LDS waits do not wait on global loads.
 #include "common.h"
 
 namespace mato {
 
-template <typename S>
-__device__ inline S dev_sqrt(S x);
-template <>
-__device__ inline float dev_sqrt<float>(float x) { return sqrtf(x); }
-template <>
-__device__ inline double dev_sqrt<double>(double x) { return sqrt(x); }
-
-// Decode the pair index p of an n-agent problem into (i, j), i < j.
-__device__ inline void decode_pair(int p, int n, int& i, int& j) {
-    const int a = 2 * n - 1;
-    int ii = (int)(((float)a - sqrtf((float)(a * a - 8 * p))) * 0.5f);
-    ii = ii < 0 ? 0 : (ii > n - 2 ? n - 2 : ii);
-    if (row_offset(ii + 1, n) <= p) ++ii;
-    if (row_offset(ii + 1, n) <= p) ++ii;
-    if (row_offset(ii, n) > p) --ii;
-    if (row_offset(ii, n) > p) --ii;
-    i = ii;
-    j = p - row_offset(ii, n) + ii + 1;
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> glob(T* p) {
+    return (gptr<T>)p;
+}
+template <typename T>
+__device__ inline gptr<const T> glob(const T* p) {
+    return (gptr<const T>)p;
 }
 
 template <typename T, int BLOCK>
@@ -73,88 +69,128 @@ __device__ inline void block_reduce3(T& mx, T& s1, T& s2, T* sh /* 3 * BLOCK/64 
     }
 }
 
+// Fast reciprocal and reciprocal square root: the hardware approximations
+// (about 1 ulp) in FP32, exact division and square root in FP64.
+template <typename S>
+struct Recip;
+template <>
+struct Recip<float> {
+    static __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+template <>
+struct Recip<double> {
+    static __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
+    static __device__ inline double rcp(double x) { return 1.0 / x; }
+};
+
 // One workgroup per work item: instants [t0, t0 + tc) of one problem, all pairs.
-// LDS: X [tc][3][n] then b_fc [tc][3][n_pairs] (scalar S).
-template <typename S, int BLOCK>
+// LDS: X [tc][3][n] (copied from the positions of the current coefficients) then
+// b_fc [tc][3][n_pairs] (scalar S).
+// Threads form `tg` instant groups of `pw` pair lanes (pw = the smallest power of two
+// >= n_pairs, between 64 and BLOCK).  A lane owns U pairs of a chunk and walks its
+// group's instants; the multipliers of the next (chunk, instant) are loaded while the
+// current one is computed, and the first ones before the positions are staged.
+template <typename S, int BLOCK, int NV, int MODE>
 __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restrict__ items,
-                                                         const ProblemDesc<S>* __restrict__ probs,
-                                                         int mode) {
+                                                         const ProblemDesc<S>* __restrict__ probs) {
+    constexpr int U = 4;
     const WorkItem it = items[blockIdx.x];
-    const ProblemDesc<S>& D = probs[it.prob];
-    if (!D.ctrl[3]) return;                          // inactive slot
-    if (mode == kModeIter && D.ctrl[1]) return;      // converged
+    const ProblemDesc<S>* __restrict__ Dp = probs + it.prob;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;                          // inactive slot
+    if (MODE == kModeIter && ctrl[1]) return;      // converged
+    const int n = Dp->n, np = Dp->np;
+    const int t0 = it.t0, tc = it.tc;
+    gptr<const S> Xm = glob((const S*)Dp->X);
+    gptr<const unsigned> pairs = glob(Dp->pairs);
+    gptr<S> lam = glob(Dp->lam);
+    gptr<S> ssum = glob(Dp->ssum);
+    gptr<const S> proj_in = glob(Dp->proj_in);
+    S* const dbg_proj_p = Dp->dbg_proj;
+    S* const dbg_d_p = Dp->dbg_d;
+    gptr<double> part = glob(Dp->part);
+    const S ia2 = Dp->ia2, ib2 = Dp->ib2, rho = Dp->srho, irho = Dp->sirho, lzl = Dp->lz;
+
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S* Xs = reinterpret_cast<S*>(smem_raw);
-    const int n = D.n, np = D.np, nv = D.nv, t0 = it.t0, tc = it.tc;
     S* Bs = Xs + tc * 3 * n;
     const int tid = threadIdx.x;
 
-    double cost = 0.0;
-    if (mode != kModeSetState) {
-        // positions X = P c at the block's instants (FP64 products, stored as S)
-        const int nX = tc * 3 * n;
-        for (int idx = tid; idx < nX; idx += BLOCK) {
-            const int tl = idx / (3 * n);
-            const int rem = idx - tl * 3 * n;
-            const int a = rem / n, i = rem - a * n;
-            const double* Pt = D.P + (size_t)(t0 + tl) * nv;
-            const double* Pddt = D.Pdd + (size_t)(t0 + tl) * nv;
-            const double* ci = D.c + (size_t)a * D.ldc + (size_t)i * nv;
-            double x = 0.0, acc = 0.0;
-            for (int k = 0; k < nv; ++k) {
-                const double ck = ci[k];
-                x += Pt[k] * ck;
-                acc += Pddt[k] * ck;
-            }
-            Xs[idx] = (S)x;
-            cost += acc * acc;
-            if (D.dbg_X) D.dbg_X[((size_t)(t0 + tl) * 3 + a) * n + i] = (S)x;
-        }
-        __syncthreads();
-    }
+    int pw = 64;
+    while (pw < np && pw < BLOCK) pw <<= 1;
+    const int tg = BLOCK / pw;
+    const int pl = tid & (pw - 1), tgid = tid / pw;
+    const int ntl = (tgid < tc) ? (tc - tgid + tg - 1) / tg : 0;   // instants of this lane's group
+    const int npb = (np + pw * U - 1) / (pw * U);                   // pair chunks
+    const int nit = npb * ntl;
 
-    const S ia2 = D.ia2, ib2 = D.ib2, rho = D.srho, irho = D.sirho, lzl = D.lz;
-    S rmax = 0, rsum = 0;
-    const int total = tc * np;
-    constexpr int U = 4;
-    for (int q0 = 0; q0 < total; q0 += BLOCK * U) {
-        S L[U][3];
-        S Pj[U][3];
+    // staged loads of one (chunk, instant): pair codes and multipliers (or d e in set-state)
+    unsigned code[U];
+    S L[U][3], Q[U][3];
+    auto fetch = [&](int k) {
+        const int pb = (k / ntl) * pw * U;
+        const int tl = tgid + (k % ntl) * tg;
+        const size_t tb = (size_t)(t0 + tl) * 3 * np;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int q = q0 + u * BLOCK + tid;
+            const int p = pb + u * pw + pl;
+            const bool ok = p < np;
+            code[u] = ok ? pairs[p] : 0u;
             L[u][0] = L[u][1] = L[u][2] = 0;
-            Pj[u][0] = Pj[u][1] = Pj[u][2] = 0;
-            if (q < total && mode != kModeInit) {
-                const int tl = q / np, p = q - tl * np;
-                const size_t base = (size_t)(t0 + tl) * 3 * np + p;
-                L[u][0] = D.lam[base];
-                L[u][1] = D.lam[base + np];
-                L[u][2] = D.lam[base + 2 * (size_t)np];
-                if (mode == kModeSetState) {
-                    Pj[u][0] = D.proj_in[base];
-                    Pj[u][1] = D.proj_in[base + np];
-                    Pj[u][2] = D.proj_in[base + 2 * (size_t)np];
+            if (MODE != kModeInit && ok) {
+                L[u][0] = __builtin_nontemporal_load(&lam[tb + p]);
+                L[u][1] = __builtin_nontemporal_load(&lam[tb + np + p]);
+                L[u][2] = __builtin_nontemporal_load(&lam[tb + 2 * (size_t)np + p]);
+            }
+            if (MODE == kModeSetState) {
+                Q[u][0] = Q[u][1] = Q[u][2] = 0;
+                if (ok) {
+                    Q[u][0] = proj_in[tb + p];
+                    Q[u][1] = proj_in[tb + np + p];
+                    Q[u][2] = proj_in[tb + 2 * (size_t)np + p];
                 }
             }
         }
+    };
+    if (nit > 0) fetch(0);
+
+    if (MODE != kModeSetState) {
+        // positions of the block's instants: one contiguous slab of X [t][3][n]
+        const int nX = tc * 3 * n;
+        gptr<const S> Xg = Xm + (size_t)t0 * 3 * n;
+        for (int idx = tid; idx < nX; idx += BLOCK) Xs[idx] = Xg[idx];
+        __syncthreads();
+    }
+
+    S rmax = 0, rsum = 0;
+    for (int k = 0; k < nit; ++k) {
+        unsigned cc[U];
+        S Lc[U][3], Qc[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int q = q0 + u * BLOCK + tid;
-            if (q >= total) continue;
-            const int tl = q / np, p = q - tl * np;
-            const size_t base = (size_t)(t0 + tl) * 3 * np + p;
-            S* Bt = Bs + (size_t)tl * 3 * np;
-            const S lx = L[u][0], ly = L[u][1], lzm = L[u][2];
-            if (mode == kModeSetState) {
-                Bt[p] = Pj[u][0] - lx * irho;
-                Bt[np + p] = Pj[u][1] - ly * irho;
-                Bt[2 * np + p] = Pj[u][2] - lzm * irho;
+            cc[u] = code[u];
+            Lc[u][0] = L[u][0]; Lc[u][1] = L[u][1]; Lc[u][2] = L[u][2];
+            if (MODE == kModeSetState) { Qc[u][0] = Q[u][0]; Qc[u][1] = Q[u][1]; Qc[u][2] = Q[u][2]; }
+        }
+        if (k + 1 < nit) fetch(k + 1);
+        const int pb = (k / ntl) * pw * U;
+        const int tl = tgid + (k % ntl) * tg;
+        const size_t tb = (size_t)(t0 + tl) * 3 * np;
+        S* Bt = Bs + (size_t)tl * 3 * np;
+        const S* X = Xs + tl * 3 * n;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = pb + u * pw + pl;
+            if (p >= np) continue;
+            const S lx = Lc[u][0], ly = Lc[u][1], lzm = Lc[u][2];
+            if (MODE == kModeSetState) {
+                Bt[p] = Qc[u][0] - lx * irho;
+                Bt[np + p] = Qc[u][1] - ly * irho;
+                Bt[2 * np + p] = Qc[u][2] - lzm * irho;
                 continue;
             }
-            int i, j;
-            decode_pair(p, n, i, j);
-            const S* X = Xs + tl * 3 * n;
+            const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
             const S dx = X[i] - X[j];
             const S dy = X[n + i] - X[n + j];
             const S dz = X[2 * n + i] - X[2 * n + j];
@@ -162,14 +198,14 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             S px, py, pz, dd;
             if (q2 > 0) {
                 const S D2 = dx * dx + dy * dy + dz * dz;
-                const S s = dev_sqrt<S>(q2);
+                const S rs = Recip<S>::rsq(q2);                     // 1 / s
                 const S dl = dx * lx + dy * ly + dz * lzm;
-                const S w = fmax(S(1) / s, S(1) + dl * irho / D2);
+                const S w = fmax(rs, S(1) + dl * irho * Recip<S>::rcp(D2));
                 px = w * dx;
                 py = w * dy;
                 pz = w * dz;
-                dd = w * s;
-            } else {                                  // delta = 0: e = (0, 0, l_z)
+                dd = w * (q2 * rs);                                 // d = w s
+            } else {                                                // delta = 0: e = (0, 0, l_z)
                 dd = fmax(S(1), lzm * irho / lzl);
                 px = 0;
                 py = 0;
@@ -177,7 +213,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             }
             const S fx = dx - px, fy = dy - py, fz = dz - pz;
             S nlx = 0, nly = 0, nlz = 0;
-            if (mode == kModeIter) {
+            if (MODE == kModeIter) {
                 nlx = lx + rho * fx;
                 nly = ly + rho * fy;
                 nlz = lzm + rho * fz;
@@ -185,134 +221,262 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
                 rmax = fmax(rmax, fn2);
                 rsum += fn2;
             }
-            D.lam[base] = nlx;
-            D.lam[base + np] = nly;
-            D.lam[base + 2 * (size_t)np] = nlz;
+            __builtin_nontemporal_store(nlx, &lam[tb + p]);
+            __builtin_nontemporal_store(nly, &lam[tb + np + p]);
+            __builtin_nontemporal_store(nlz, &lam[tb + 2 * (size_t)np + p]);
             Bt[p] = px - nlx * irho;
             Bt[np + p] = py - nly * irho;
             Bt[2 * np + p] = pz - nlz * irho;
-            if (D.dbg_proj) {
-                D.dbg_proj[base] = px;
-                D.dbg_proj[base + np] = py;
-                D.dbg_proj[base + 2 * (size_t)np] = pz;
+            if (dbg_proj_p) {
+                gptr<S> dp = glob(dbg_proj_p);
+                dp[tb + p] = px;
+                dp[tb + np + p] = py;
+                dp[tb + 2 * (size_t)np + p] = pz;
             }
-            if (D.dbg_d) D.dbg_d[(size_t)(t0 + tl) * np + p] = dd;
+            if (dbg_d_p) glob(dbg_d_p)[(size_t)(t0 + tl) * np + p] = dd;
         }
     }
     __syncthreads();
 
     // S_i(t) = sum_{j<i} (-b_ji) + sum_{j>i} b_ij, j ascending (fixed order)
-    const int nS = tc * 3 * n;
+    const int n3 = 3 * n;
+    const int nS = tc * n3;
     for (int o = tid; o < nS; o += BLOCK) {
-        const int tl = o / (3 * n);
-        const int rem = o - tl * 3 * n;
+        const int tl = o / n3;
+        const int rem = o - tl * n3;
         const int a = rem / n, i = rem - a * n;
         const S* Bt = Bs + ((size_t)tl * 3 + a) * np;
         S acc = 0;
         int pj = i - 1;
+#pragma unroll 8
         for (int j = 0; j < i; ++j) {
             acc -= Bt[pj];
             pj += n - j - 2;
         }
-        const int base = row_offset(i, n) - i - 1;
-        for (int j = i + 1; j < n; ++j) acc += Bt[base + j];
-        D.ssum[((size_t)(t0 + tl) * 3 + a) * n + i] = acc;
+        const S* row = Bt + row_offset(i, n) - i - 1;
+#pragma unroll 8
+        for (int j = i + 1; j < n; ++j) acc += row[j];
+        ssum[((size_t)(t0 + tl) * 3 + a) * n + i] = acc;
     }
 
-    if (mode == kModeIter) {
+    if (MODE == kModeIter) {
         __shared__ double red[3 * (BLOCK / 64)];
-        double mx = (double)rmax, s1 = (double)rsum, s2 = cost;
+        double mx = (double)rmax, s1 = (double)rsum, s2 = 0.0;
         block_reduce3<double, BLOCK>(mx, s1, s2, red);
         if (tid == 0) {
-            double* pp = D.part + (size_t)it.slab * 4;
+            gptr<double> pp = part + (size_t)it.slab * 4;
             pp[0] = mx;
             pp[1] = s1;
-            pp[2] = s2;
         }
     }
 }
 
-// One workgroup per problem: g = rho P^T S (FP64) into q[a][0 .. n*nv), then in
-// iteration mode the residual record of this iteration and the convergence test.
-template <typename S>
+// One workgroup per problem: X = P c (eq. (param)) at every instant, in FP64 products
+// stored as S, and the smoothness cost sum (Pddot c)^2 of eq. (cost_proposed).  A
+// thread owns (axis, agent) columns; the basis rows are staged in LDS in chunks of
+// 32 instants.
+template <typename S, int NV>
+__global__ __launch_bounds__(256) void positions_kernel(const ProblemDesc<S>* __restrict__ probs, int mode) {
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;
+    if (mode == kModeIter && ctrl[1]) return;
+    const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldc = Dp->ldc;
+    gptr<const double> Pm = glob(Dp->P);
+    gptr<const double> Pddm = glob(Dp->Pdd);
+    gptr<const double> cm = glob((const double*)Dp->c);
+    gptr<S> Xm = glob(Dp->X);
+    constexpr int TC = 32;
+    __shared__ double Ps[TC * kMaxCoef], Pdds[TC * kMaxCoef];
+    __shared__ double red[3 * 4];
+    const int n3 = 3 * n;
+    double cost = 0.0;
+    for (int tb = 0; tb < T; tb += TC) {
+        const int tn = min(TC, T - tb);
+        __syncthreads();
+        for (int e = threadIdx.x; e < tn * nv; e += blockDim.x) {
+            Ps[e] = Pm[(size_t)tb * nv + e];
+            Pdds[e] = Pddm[(size_t)tb * nv + e];
+        }
+        __syncthreads();
+        for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+            const int a = col / n, i = col - a * n;
+            gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * nv;
+            if constexpr (NV > 0) {
+                double cv[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) cv[k] = ci[k];
+                for (int t = 0; t < tn; ++t) {
+                    double x = 0.0, acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        x += Ps[t * NV + k] * cv[k];
+                        acc += Pdds[t * NV + k] * cv[k];
+                    }
+                    Xm[(size_t)(tb + t) * n3 + col] = (S)x;
+                    cost += acc * acc;
+                }
+            } else {
+                for (int t = 0; t < tn; ++t) {
+                    double x = 0.0, acc = 0.0;
+                    for (int k = 0; k < nv; ++k) {
+                        x += Ps[t * nv + k] * ci[k];
+                        acc += Pdds[t * nv + k] * ci[k];
+                    }
+                    Xm[(size_t)(tb + t) * n3 + col] = (S)x;
+                    cost += acc * acc;
+                }
+            }
+        }
+    }
+    double z0 = 0.0, z1 = 0.0;
+    block_reduce3<double, 256>(z0, cost, z1, red);
+    if (threadIdx.x == 0) glob(Dp->misc)[0] = cost;
+}
+
+// One workgroup per problem: g = rho P^T S (FP64) into q[a][0 .. n*nv) (and its FP32
+// copy), then in iteration mode the residual record of this iteration and the
+// convergence test.  A thread owns one (axis, agent) column of S and produces its
+// nv coefficients.
+template <typename S, int NV>
 __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __restrict__ probs, int mode) {
-    const ProblemDesc<S>& D = probs[blockIdx.x];
-    if (!D.ctrl[3]) return;
-    if (mode == kModeIter && D.ctrl[1]) return;
-    const int n = D.n, nv = D.nv, T = D.T;
-    const int tot = 3 * n * nv;
-    for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-        const int a = o / (n * nv);
-        const int rem = o - a * n * nv;
-        const int i = rem / nv, k = rem - i * nv;
-        double acc = 0.0;
-        const S* sp = D.ssum + (size_t)a * n + i;
-        for (int t = 0; t < T; ++t) acc += D.P[(size_t)t * nv + k] * (double)sp[(size_t)t * 3 * n];
-        D.q[(size_t)a * D.ldq + rem] = D.rho * acc;
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<int> ctrl = glob(Dp->ctrl);
+    if (!ctrl[3]) return;
+    if (mode == kModeIter && ctrl[1]) return;
+    const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldq = Dp->ldq;
+    const double rho = Dp->rho;
+    gptr<const double> Pm = glob(Dp->P);
+    gptr<const S> ss = glob((const S*)Dp->ssum);
+    gptr<double> q = glob(Dp->q);
+    gptr<float> qf = glob(Dp->qf);
+    const int n3 = 3 * n;
+    for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+        const int a = col / n, i = col - a * n;
+        gptr<const S> sp = ss + col;                 // [(t*3 + a)*n + i] = t*3n + col
+        const size_t o = (size_t)a * ldq + (size_t)i * nv;
+        if constexpr (NV > 0) {
+            double acc[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+            int t = 0;
+            for (; t + 8 <= T; t += 8) {
+                double sv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sv[u] = (double)sp[(size_t)(t + u) * n3];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) acc[k] += Pm[(size_t)(t + u) * NV + k] * sv[u];
+            }
+            for (; t < T; ++t) {
+                const double sv = (double)sp[(size_t)t * n3];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) acc[k] += Pm[(size_t)t * NV + k] * sv;
+            }
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                q[o + k] = rho * acc[k];
+                qf[o + k] = (float)(rho * acc[k]);
+            }
+        } else {
+            for (int k = 0; k < nv; ++k) {
+                double acc = 0.0;
+                for (int t = 0; t < T; ++t) acc += Pm[(size_t)t * nv + k] * (double)sp[(size_t)t * n3];
+                q[o + k] = rho * acc;
+                qf[o + k] = (float)(rho * acc);
+            }
+        }
     }
     if (mode == kModeIter && threadIdx.x == 0) {
-        double mx = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int k = 0; k < D.nslab; ++k) {
-            const double* pp = D.part + (size_t)k * 4;
-            mx = fmax(mx, pp[0]);
-            s1 += pp[1];
-            s2 += pp[2];
+        gptr<const double> part = glob((const double*)Dp->part);
+        gptr<double> hist = glob(Dp->hist);
+        const int nslab = Dp->nslab;
+        double mx = 0.0, s1 = 0.0;
+        for (int k = 0; k < nslab; ++k) {
+            mx = fmax(mx, part[(size_t)k * 4 + 0]);
+            s1 += part[(size_t)k * 4 + 1];
         }
-        const int it = D.ctrl[0];
+        const double s2 = glob((const double*)Dp->misc)[0];
+        const int itn = ctrl[0];
         const double rmax = sqrt(mx);
-        if (it < D.hist_cap) {
-            D.hist[(size_t)it * 3 + 0] = rmax;
-            D.hist[(size_t)it * 3 + 1] = sqrt(s1 / ((double)D.np * (double)T));
-            D.hist[(size_t)it * 3 + 2] = s2;
+        if (itn < Dp->hist_cap) {
+            hist[(size_t)itn * 3 + 0] = rmax;
+            hist[(size_t)itn * 3 + 1] = sqrt(s1 / ((double)Dp->np * (double)T));
+            hist[(size_t)itn * 3 + 2] = s2;
         }
-        D.ctrl[0] = it + 1;
+        ctrl[0] = itn + 1;
         if (!isfinite(s1) || !isfinite(s2)) {
-            D.ctrl[2] = 1;
-            D.ctrl[1] = 1;
-        } else if (D.tol > 0.0 && rmax < D.tol) {
-            D.ctrl[1] = 1;
+            ctrl[2] = 1;
+            ctrl[1] = 1;
+        } else if (Dp->tol > 0.0 && rmax < Dp->tol) {
+            ctrl[1] = 1;
         }
     }
 }
 
-// grid (problems, 3 axes): r = [g - H c ; b_eq - A c] in FP64.
+// grid (problems, 3 axes): r = g - H c in FP64 (and its FP32 copy).  The boundary
+// rows of the correction are not formed: K11^{-1} A^T = 0, and the boundary
+// coefficients of c come from c_eq exactly.
 template <typename S>
 __global__ __launch_bounds__(256) void residual_kernel(const ProblemDesc<S>* __restrict__ probs) {
-    const ProblemDesc<S>& D = probs[blockIdx.x];
-    if (!D.ctrl[3] || D.ctrl[1]) return;
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3] || ctrl[1]) return;
     const int a = blockIdx.y;
-    const int n = D.n, nv = D.nv;
-    const double* c = D.c + (size_t)a * D.ldc;
-    const double* q = D.q + (size_t)a * D.ldq;
-    double* r = D.r + (size_t)a * D.ldq;
+    const int n = Dp->n, nv = Dp->nv, ldq = Dp->ldq;
+    const double rho = Dp->rho;
+    gptr<const double> c = glob((const double*)Dp->c) + (size_t)a * Dp->ldc;
+    gptr<const double> q = glob((const double*)Dp->q) + (size_t)a * ldq;
+    gptr<double> r = glob(Dp->r) + (size_t)a * ldq;
+    gptr<float> rf = glob(Dp->rf) + (size_t)a * ldq;
     __shared__ double csum[kMaxCoef];
-    __shared__ double PtP[kMaxCoef * kMaxCoef], PddtPdd[kMaxCoef * kMaxCoef], A[kNb * kMaxCoef];
+    __shared__ double PtP[kMaxCoef * kMaxCoef], PddtPdd[kMaxCoef * kMaxCoef];
+    __shared__ double cs[kMaxCoef * MATO_MAX_AGENTS];
+    gptr<const double> gPtP = glob(Dp->PtP), gPddtPdd = glob(Dp->PddtPdd);
     for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) {
-        PtP[e] = D.PtP[e];
-        PddtPdd[e] = D.PddtPdd[e];
+        PtP[e] = gPtP[e];
+        PddtPdd[e] = gPddtPdd[e];
     }
-    for (int e = threadIdx.x; e < kNb * nv; e += blockDim.x) A[e] = D.A[e];
+    for (int e = threadIdx.x; e < n * nv; e += blockDim.x) cs[e] = c[e];
+    __syncthreads();
     if (threadIdx.x < nv) {
         double s = 0.0;
-        for (int j = 0; j < n; ++j) s += c[(size_t)j * nv + threadIdx.x];
+        for (int j = 0; j < n; ++j) s += cs[j * nv + threadIdx.x];
         csum[threadIdx.x] = s;
     }
     __syncthreads();
-    const double nr = (double)n * D.rho;
+    const double nr = (double)n * rho;
     for (int o = threadIdx.x; o < n * nv; o += blockDim.x) {
         const int i = o / nv, k = o - i * nv;
-        const double* ci = c + (size_t)i * nv;
+        const double* ci = cs + i * nv;
         double h = 0.0;
         for (int l = 0; l < nv; ++l)
-            h += PddtPdd[k * nv + l] * ci[l] + PtP[k * nv + l] * (nr * ci[l] - D.rho * csum[l]);
-        r[o] = q[o] - h;
+            h += PddtPdd[k * nv + l] * ci[l] + PtP[k * nv + l] * (nr * ci[l] - rho * csum[l]);
+        const double v = q[o] - h;
+        r[o] = v;
+        rf[o] = (float)v;
     }
-    for (int o = threadIdx.x; o < n * kNb; o += blockDim.x) {
-        const int i = o / kNb, bb = o - i * kNb;
-        const double* ci = c + (size_t)i * nv;
-        double h = 0.0;
-        for (int l = 0; l < nv; ++l) h += A[bb * nv + l] * ci[l];
-        r[n * nv + o] = q[n * nv + o] - h;
+}
+
+// grid (problems, 3 axes): c_eq = K12^{-1} b_eq in FP64 (b_eq has the start in row 0
+// and the goal in row 3 of each agent's six boundary rows, zeros elsewhere).
+template <typename S>
+__global__ __launch_bounds__(256) void ceq_kernel(const ProblemDesc<S>* __restrict__ probs,
+                                                  const double* const* __restrict__ kinv) {
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;
+    const int a = blockIdx.y;
+    const int n = Dp->n, nv = Dp->nv, M = n * nv, N = n * (nv + kNb);
+    gptr<const double> K = glob(kinv[blockIdx.x]);
+    gptr<const double> beq = glob((const double*)Dp->q) + (size_t)a * Dp->ldq + M;
+    gptr<double> ceq = glob(Dp->ceq) + (size_t)a * Dp->ldc;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        gptr<const double> row = K + (size_t)m * N + M;
+        double v = 0.0;
+        for (int i = 0; i < n; ++i) v += row[i * kNb + 0] * beq[i * kNb + 0] + row[i * kNb + 3] * beq[i * kNb + 3];
+        ceq[m] = v;
     }
 }
 
@@ -320,56 +484,104 @@ __global__ __launch_bounds__(256) void residual_kernel(const ProblemDesc<S>* __r
 template <typename S>
 __global__ __launch_bounds__(256) void init_kernel(const ProblemDesc<S>* __restrict__ probs,
                                                    const double* const* __restrict__ k0c) {
-    const ProblemDesc<S>& D = probs[blockIdx.x];
-    if (!D.ctrl[3]) return;
-    const int n = D.n, nv = D.nv;
-    const double* K0 = k0c[blockIdx.x];
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;
+    const int n = Dp->n, nv = Dp->nv, ldq = Dp->ldq, ldc = Dp->ldc;
+    gptr<const double> K0 = glob(k0c[blockIdx.x]);
+    gptr<const double> q = glob((const double*)Dp->q);
+    gptr<double> c = glob(Dp->c);
     for (int o = threadIdx.x; o < 3 * n * nv; o += blockDim.x) {
         const int a = o / (n * nv);
         const int rem = o - a * n * nv;
         const int i = rem / nv, k = rem - i * nv;
-        const double* beq = D.q + (size_t)a * D.ldq + (size_t)n * nv + (size_t)i * kNb;
+        gptr<const double> beq = q + (size_t)a * ldq + (size_t)n * nv + (size_t)i * kNb;
         double v = 0.0;
         for (int bb = 0; bb < kNb; ++bb) v += K0[k * kNb + bb] * beq[bb];
-        D.c[(size_t)a * D.ldc + rem] = v;
+        c[(size_t)a * ldc + rem] = v;
     }
 }
 
 // ------------------------------------------------------------- launchers ---
-template <typename S>
-hipError_t launch_pairwise(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
-                           int threads, size_t lds, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
+template <typename S, int NV, int MODE>
+static hipError_t launch_pw(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int threads,
+                            size_t lds, hipStream_t st) {
     switch (threads) {
         case 256:
-            pairwise_kernel<S, 256><<<nitems, 256, lds, st>>>(items, probs, mode);
+            pairwise_kernel<S, 256, NV, MODE><<<nitems, 256, lds, st>>>(items, probs);
             break;
         case 512:
-            pairwise_kernel<S, 512><<<nitems, 512, lds, st>>>(items, probs, mode);
+            pairwise_kernel<S, 512, NV, MODE><<<nitems, 512, lds, st>>>(items, probs);
             break;
         default:
-            pairwise_kernel<S, 1024><<<nitems, 1024, lds, st>>>(items, probs, mode);
+            pairwise_kernel<S, 1024, NV, MODE><<<nitems, 1024, lds, st>>>(items, probs);
             break;
     }
     return hipGetLastError();
 }
 
+template <typename S, int NV>
+static hipError_t launch_pw_mode(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
+                                 int threads, size_t lds, hipStream_t st) {
+    if (mode == kModeIter) return launch_pw<S, NV, kModeIter>(items, nitems, probs, threads, lds, st);
+    if (mode == kModeInit) return launch_pw<S, NV, kModeInit>(items, nitems, probs, threads, lds, st);
+    return launch_pw<S, NV, kModeSetState>(items, nitems, probs, threads, lds, st);
+}
+
+// nv: the (common) number of basis coefficients of the launch's problems, or 0 if they differ.
 template <typename S>
-hipError_t set_pairwise_lds_limit(size_t lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 256>,
+hipError_t launch_pairwise(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
+                           int threads, size_t lds, int nv, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, threads, lds, st);
+    return launch_pw_mode<S, 0>(items, nitems, probs, mode, threads, lds, st);
+}
+
+template <typename S, int NV, int MODE>
+static hipError_t set_lds_one(size_t lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 256, NV, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 512>,
+    e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 512, NV, MODE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)pairwise_kernel<S, 1024>,
+    return hipFuncSetAttribute((const void*)pairwise_kernel<S, 1024, NV, MODE>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+template <typename S, int NV>
+static hipError_t set_lds_nv(size_t lds) {
+    hipError_t e = set_lds_one<S, NV, kModeIter>(lds);
+    if (e != hipSuccess) return e;
+    e = set_lds_one<S, NV, kModeInit>(lds);
+    if (e != hipSuccess) return e;
+    return set_lds_one<S, NV, kModeSetState>(lds);
+}
+
 template <typename S>
-hipError_t launch_qbuild(const ProblemDesc<S>* probs, int nprob, int mode, hipStream_t st) {
+hipError_t set_pairwise_lds_limit(size_t lds) {
+    hipError_t e = set_lds_nv<S, 11>(lds);
+    if (e != hipSuccess) return e;
+    return set_lds_nv<S, 0>(lds);
+}
+
+template <typename S>
+hipError_t launch_qbuild(const ProblemDesc<S>* probs, int nprob, int mode, int nv, hipStream_t st) {
     if (nprob <= 0) return hipSuccess;
-    qbuild_kernel<S><<<nprob, 256, 0, st>>>(probs, mode);
+    if (nv == 11)
+        qbuild_kernel<S, 11><<<nprob, 256, 0, st>>>(probs, mode);
+    else
+        qbuild_kernel<S, 0><<<nprob, 256, 0, st>>>(probs, mode);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_positions(const ProblemDesc<S>* probs, int nprob, int mode, int nv, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    if (nv == 11)
+        positions_kernel<S, 11><<<nprob, 256, 0, st>>>(probs, mode);
+    else
+        positions_kernel<S, 0><<<nprob, 256, 0, st>>>(probs, mode);
     return hipGetLastError();
 }
 
@@ -381,20 +593,31 @@ hipError_t launch_residual(const ProblemDesc<S>* probs, int nprob, hipStream_t s
 }
 
 template <typename S>
+hipError_t launch_ceq(const ProblemDesc<S>* probs, const double* const* kinv, int nprob, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    ceq_kernel<S><<<dim3(nprob, 3), 256, 0, st>>>(probs, kinv);
+    return hipGetLastError();
+}
+
+template <typename S>
 hipError_t launch_init(const ProblemDesc<S>* probs, const double* const* k0c, int nprob, hipStream_t st) {
     if (nprob <= 0) return hipSuccess;
     init_kernel<S><<<nprob, 256, 0, st>>>(probs, k0c);
     return hipGetLastError();
 }
 
-template hipError_t launch_pairwise<float>(const WorkItem*, int, const ProblemDesc<float>*, int, int, size_t, hipStream_t);
-template hipError_t launch_pairwise<double>(const WorkItem*, int, const ProblemDesc<double>*, int, int, size_t, hipStream_t);
+template hipError_t launch_pairwise<float>(const WorkItem*, int, const ProblemDesc<float>*, int, int, size_t, int, hipStream_t);
+template hipError_t launch_pairwise<double>(const WorkItem*, int, const ProblemDesc<double>*, int, int, size_t, int, hipStream_t);
 template hipError_t set_pairwise_lds_limit<float>(size_t);
 template hipError_t set_pairwise_lds_limit<double>(size_t);
-template hipError_t launch_qbuild<float>(const ProblemDesc<float>*, int, int, hipStream_t);
-template hipError_t launch_qbuild<double>(const ProblemDesc<double>*, int, int, hipStream_t);
+template hipError_t launch_qbuild<float>(const ProblemDesc<float>*, int, int, int, hipStream_t);
+template hipError_t launch_qbuild<double>(const ProblemDesc<double>*, int, int, int, hipStream_t);
+template hipError_t launch_positions<float>(const ProblemDesc<float>*, int, int, int, hipStream_t);
+template hipError_t launch_positions<double>(const ProblemDesc<double>*, int, int, int, hipStream_t);
 template hipError_t launch_residual<float>(const ProblemDesc<float>*, int, hipStream_t);
 template hipError_t launch_residual<double>(const ProblemDesc<double>*, int, hipStream_t);
+template hipError_t launch_ceq<float>(const ProblemDesc<float>*, const double* const*, int, hipStream_t);
+template hipError_t launch_ceq<double>(const ProblemDesc<double>*, const double* const*, int, hipStream_t);
 template hipError_t launch_init<float>(const ProblemDesc<float>*, const double* const*, int, hipStream_t);
 template hipError_t launch_init<double>(const ProblemDesc<double>*, const double* const*, int, hipStream_t);
 

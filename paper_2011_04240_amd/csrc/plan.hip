@@ -187,7 +187,7 @@ __device__ inline float bf16_bits_to_float(unsigned short h) {
     return __uint_as_float(((unsigned int)h) << 16);
 }
 
-// GEMM operand: rows 0..M-1 of K^{-1} (all N columns), zero-padded to Mp x ldk.
+// GEMM operand: the leading M x M block of K^{-1} (row stride N), zero-padded to Mp x ldk.
 // kind 0: fp32; 1: bf16 hi + lo (hi = bf16(x), lo = bf16(fp32(x) - hi)); 2: fp64.
 __global__ void extract_crows(const double* __restrict__ inv, int N, int M, int Mp, int ldk,
                               int kind, void* __restrict__ hi, void* __restrict__ lo) {
@@ -195,7 +195,7 @@ __global__ void extract_crows(const double* __restrict__ inv, int N, int M, int 
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / ldk), c = (int)(e % ldk);
-        const double v = (r < M && c < N) ? inv[(size_t)r * N + c] : 0.0;
+        const double v = (r < M && c < M) ? inv[(size_t)r * N + c] : 0.0;
         if (kind == 0) {
             ((float*)hi)[e] = (float)v;
         } else if (kind == 1) {
@@ -284,6 +284,12 @@ static mato_status plan_build(mato_plan p) {
     MATO_TRY(upload(&p->dPtP, p->PtP, &p->bytes));
     MATO_TRY(upload(&p->dPddtPdd, p->PddtPdd, &p->bytes));
     MATO_TRY(upload(&p->dA, p->A, &p->bytes));
+    {
+        std::vector<unsigned> pairs;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) pairs.push_back((unsigned)i | ((unsigned)j << 16));
+        MATO_TRY(upload(&p->dPairs, pairs, &p->bytes));
+    }
 
     // boundary-only minimum-acceleration KKT (initialisation): [[Pdd^T Pdd, A^T], [A, 0]]
     {
@@ -325,9 +331,10 @@ static mato_status plan_build(mato_plan p) {
     dfree(W);
     if (s != MATO_OK) return s;
 
-    // GEMM operand: c-rows [K11^{-1} | K12^{-1}]
+    // GEMM operand: the (11n x 11n) block K11^{-1}; the K12^{-1} b_eq part is formed once
+    // per problem in FP64
     const int Mp = round_up(M, 64);
-    p->ldk = round_up(N, 32);
+    p->ldk = round_up(M, 32);
     const size_t elems = (size_t)Mp * p->ldk;
     int kind = 0;
     size_t esz = sizeof(float);
@@ -361,6 +368,7 @@ extern "C" void mato_plan_destroy(mato_plan p) {
     dfree(p->dPddtPdd);
     dfree(p->dA);
     dfree(p->dK0c);
+    dfree(p->dPairs);
     dfree(p->dAhi);
     dfree(p->dAlo);
     delete p;

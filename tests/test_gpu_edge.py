@@ -1,0 +1,155 @@
+"""GPU edge cases and batching through the C ABI, against the FP64 oracle.
+
+* smallest problem (n = 2, one pair) at the smallest horizon (T = n_coef);
+* largest problem (n = MATO_MAX_AGENTS, one instant of all pairs fills the LDS);
+* coincident agents (delta = 0 exactly, the alpha = beta = 0 branch);
+* uneven-size problems in one batch give bitwise the same iterates as alone;
+* error paths: non-finite input, invalid problem index, NOT_CONVERGED warning.
+"""
+import numpy as np
+import pytest
+
+from oracle import am
+from paper_2011_04240_amd import mato
+from paper_2011_04240_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+def test_two_agents_minimum_horizon(precision, tol):
+    say("n=2 T=11", precision)
+    s = np.array([[0.0, 0.0, 0.0], [0.3, 0.05, 0.0]])
+    g = np.array([[0.3, 0.0, 0.0], [0.0, 0.05, 0.0]])
+    op = am.make_plan(2, 11, 11, 2.0, 0.4, 0.8, 1.0)
+    st = am.solve(op, s, g, 40)
+    b = mato.Batch([mato.Plan(2, 11, 11, 2.0, 0.4, 0.8, 1.0, precision)], [s], [g])
+    b.run(40, 0.0, 10)
+    r_max, _, cost = b.residuals(0)
+    assert rel(b.coeffs(0), st.c) < tol
+    assert rel(r_max, st.history["r_max"]) < tol
+    assert rel(cost, st.history["cost"]) < tol
+
+
+def test_largest_problem_single_step():
+    n, T = mato.MATO_MAX_AGENTS, 24
+    say("n=%d T=%d single step" % (n, T))
+    s, g = sc.random_density_box(n, seed=5)
+    op = am.make_plan(n, T, 11, 3.0, 0.3, 0.6, 1.0)
+    st = am.initial_state(op, s, g)
+    st = am.iterate(op, st)
+    lam = st.lam.astype(np.float32)
+    proj = st.proj(op).astype(np.float32)
+    ref = am.iterate_rhs(op, proj.astype(np.float64) - lam.astype(np.float64), lam.astype(np.float64), st.beq)
+    b = mato.Batch([mato.Plan(n, T, 11, 3.0, 0.3, 0.6, 1.0, "fp32")], [s], [g])
+    b.set_state(0, st.c, lam, proj)
+    b.step(1, use_graph=False)
+    out = b.get_state(0)
+    assert rel(out["c"], ref["c"]) < 1e-5
+    assert rel(out["lam"], ref["lam"]) < 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-5)])
+def test_coincident_agents(precision, tol):
+    """Agents 0 and 1 share start and goal: delta is exactly 0 along the boundary-only
+    trajectories, so the initial projection takes e = (0, 0, l_z)."""
+    say("coincident agents", precision)
+    s = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [3.0, 0.0, 1.0], [-2.0, 1.0, 0.5]])
+    g = np.array([[2.0, 1.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, -1.0, 0.5]])
+    op = am.make_plan(4, 30, 11, 4.0, 0.4, 0.8, 1.0)
+    st0 = am.initial_state(op, s, g)
+    assert np.all(st0.delta[0] == 0.0)
+    b = mato.Batch([mato.Plan(4, 30, 11, 4.0, 0.4, 0.8, 1.0, precision)], [s], [g])
+    g_ref = am.linear_term(op, am.collision_rhs(op, st0.d, st0.alpha, st0.beta, st0.lam))
+    assert rel(b.linear_term(0), g_ref) < tol
+    st = am.solve(op, s, g, 5)
+    b.step(5, use_graph=False)
+    assert rel(b.coeffs(0), st.c) < (tol if precision == "fp64" else 1e-4)
+
+
+def test_uneven_batch_matches_alone_bitwise():
+    say("uneven batch vs alone")
+    ns = [5, 13, 8, 21, 13, 37, 5]
+    plans = {n: mato.Plan(n, 40, 11, 5.0, 0.3, 0.6, 1.0, "fp32") for n in set(ns)}
+    scen = [sc.random_density_box(n, seed=10 + q) for q, n in enumerate(ns)]
+    mix = mato.Batch([plans[n] for n in ns], [x[0] for x in scen], [x[1] for x in scen])
+    mix.step(25, use_graph=True)
+    mix.sync()
+    for q, n in enumerate(ns):
+        alone = mato.Batch([plans[n]], [scen[q][0]], [scen[q][1]])
+        alone.step(25, use_graph=False)
+        a, m = alone.get_state(0), mix.get_state(q)
+        np.testing.assert_array_equal(a["c"], m["c"])
+        np.testing.assert_array_equal(a["lam"], m["lam"])
+        np.testing.assert_array_equal(alone.residuals(0)[0], mix.residuals(q)[0])
+
+
+def test_batch_matches_oracle_per_problem():
+    say("uneven batch vs oracle")
+    ns = [6, 11, 17]
+    scen = [sc.random_density_box(n, seed=40 + q) for q, n in enumerate(ns)]
+    b = mato.Batch([mato.Plan(n, 30, 11, 4.0, 0.3, 0.6, 1.0, "fp64") for n in ns],
+                   [x[0] for x in scen], [x[1] for x in scen])
+    b.run(30, 0.0, 10)
+    for q, n in enumerate(ns):
+        st = am.solve(am.make_plan(n, 30, 11, 4.0, 0.3, 0.6, 1.0), scen[q][0], scen[q][1], 30)
+        assert rel(b.coeffs(q), st.c) < 1e-8
+        assert rel(b.residuals(q)[0], st.history["r_max"]) < 1e-8
+
+
+def test_convergence_stop_and_warning():
+    say("tolerance stop")
+    s, g = sc.swap_circle(4, seed=0)
+    b = mato.Batch([mato.Plan(4, 50, 11, 5.0, 0.4, 0.8, 1.0, "fp64")], [s], [g])
+    assert b.run(500, 0.05, 7) == mato.MATO_OK
+    it, conv = b.status(0)
+    r_max, _, _ = b.residuals(0)
+    assert conv and r_max[-1] < 0.05 and np.all(r_max[:-1] >= 0.05) and it == len(r_max)
+    ref = am.solve(am.make_plan(4, 50, 11, 5.0, 0.4, 0.8, 1.0), s, g, 500, tol=0.05)
+    assert it == len(ref.history["r_max"])
+    b2 = mato.Batch([mato.Plan(4, 50, 11, 5.0, 0.4, 0.8, 1.0, "fp32")], [s], [g])
+    assert b2.run(5, 1e-9, 5) == mato.MATO_WARN_NOT_CONVERGED
+
+
+def test_error_paths():
+    say("error paths")
+    p = mato.Plan(4, 20, 11, 3.0, 0.4, 0.8, 1.0, "fp32")
+    s, g = sc.swap_circle(4, seed=1)
+    bad = s.copy()
+    bad[2, 1] = np.nan
+    with pytest.raises(mato.MatoError) as e:
+        mato.Batch([p], [bad], [g])
+    assert e.value.status == mato.MATO_ERR_NONFINITE
+    b = mato.Batch([p], [s], [g])
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_batch_coeffs(b.handle, 1, np.empty((4, 3, 11)))
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
+    p64 = mato.Plan(4, 20, 11, 3.0, 0.4, 0.8, 1.0, "fp64")
+    with pytest.raises(mato.MatoError):
+        mato.Batch([p, p64], [s, s], [g, g])          # mixed precisions
+
+
+def test_autotune_keeps_results():
+    say("autotune")
+    ns = [8, 24]
+    scen = [sc.random_density_box(n, seed=70 + q) for q, n in enumerate(ns)]
+    plans = [mato.Plan(n, 50, 11, 5.0, 0.3, 0.6, 1.0, "fp32") for n in ns]
+    ref = mato.Batch(plans, [x[0] for x in scen], [x[1] for x in scen])
+    ref.step(10)
+    tuned = mato.Batch(plans, [x[0] for x in scen], [x[1] for x in scen])
+    ipw, thr = tuned.autotune()
+    assert thr in (256, 512, 1024) and ipw >= 1
+    tuned.step(10)
+    for q in range(2):
+        np.testing.assert_array_equal(ref.get_state(q)["lam"], tuned.get_state(q)["lam"])
