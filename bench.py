@@ -1,14 +1,18 @@
 """Benchmark of the alternating-minimisation iteration on one MI355X.
 
 One step = one iteration of Algorithm 1 (inverse product with its FP64
-refinement, fused pairwise stage, linear term) over a batch of B independent
-random-box problems with n = 64 agents and T = 100 instants (seeded synthetic
-start/goal positions: uniform in a 10 x 10 x 5 m box, at least 1 m apart).
+refinement, positions, fused pairwise stage, linear term) over a batch of B
+independent random-box problems with n = 64 agents and T = 100 instants (seeded
+synthetic start/goal positions: uniform in a 10 x 10 x 5 m box, at least 1 m apart).
 
 Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step),
 the roofline of the pairwise kernel (24 algorithmic bytes per pair-instant:
 the FP32 multipliers read and written), timed with HIP events on the batch's
-stream, and the FP64 oracle timed on the host on a bounded sample.
+stream, and the FP64 oracle timed on the host on a bounded sample.  Also in the
+line: served p50/p99 solve latency of a short Poisson trace through the
+continuous-batching server (agent counts 4..128), and uneven-size batching
+(256 problems, n in {8, 12, ..., 48}) against the same problems solved one at a
+time.  `--serve-sweep` replaces all of this by the latency sweep over arrival rates.
 """
 import argparse
 import hashlib
@@ -41,6 +45,13 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=100.0)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only run the served-latency sweep over arrival rates 10..500 /s")
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16"])
     return ap.parse_args()
 
 
@@ -92,6 +103,67 @@ def cpu_baseline(n, T, seconds):
                       % (n, T, iters, dt)}
 
 
+def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_iters=2000, tol=1e-3):
+    """Poisson arrivals of random-box problems (n uniform over 4..128, box at the n=64
+    density) replayed in real time through the server; latency = finish - arrival."""
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    ns = [int(x) for x in rng.integers(4, 129, size=count)]
+    scen = [sc.random_density_box(n, seed=10000 * (seed + 1) + k) for k, n in enumerate(ns)]
+    arr = sc.poisson_arrivals(rate, count, seed=seed)
+    srv = mato.Server(T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision=precision,
+                      max_slots=max_slots, chunk=chunk, max_iters=max_iters, tol=tol)
+    t0 = time.perf_counter()
+    srv.warm(4, 128)
+    warm_s = time.perf_counter() - t0
+    lat, its, conv, wall = srv.run_trace(arr, [x[0] for x in scen], [x[1] for x in scen])
+    srv.close()
+    upd = sum(n * (n - 1) // 2 * 100 * int(k) for n, k in zip(ns, its))
+    return {"rate_per_s": rate, "requests": count, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(np.mean(lat) * 1e3),
+            "throughput_problems_per_s": count / wall, "updates_per_s": upd / wall,
+            "converged_frac": float(np.mean(conv)), "capped_frac": float(np.mean(its >= max_iters)),
+            "mean_iters": float(np.mean(its)), "wall_s": wall, "plan_warm_s": warm_s,
+            "precision": precision, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol}
+
+
+def mixed_batching(count=256, iters=30, seed=0):
+    """Uneven sizes in one launch per stage (graph-replayed, autotuned tiles) against the
+    plain per-problem method (each problem alone, separate launches, no graphs)."""
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+    ns = sc.agent_counts(count, list(range(8, 49, 4)), seed=seed)
+    scen = [sc.random_box(n, seed=20000 + k) for k, n in enumerate(ns)]
+    plans = {n: mato.Plan(n, 100, 11, 10.0, 0.3, 0.6, 1.0, "fp32") for n in sorted(set(ns))}
+    batch = mato.Batch([plans[n] for n in ns], [x[0] for x in scen], [x[1] for x in scen])
+    tiles = batch.autotune()
+    batch.step(3)
+    batch.sync()
+    t0 = time.perf_counter()
+    batch.step(iters, use_graph=True)
+    batch.sync()
+    t_batch = time.perf_counter() - t0
+    solo = [mato.Batch([plans[n]], [scen[k][0]], [scen[k][1]]) for k, n in enumerate(ns)]
+    for b in solo:
+        b.step(1, use_graph=False)
+    for b in solo:
+        b.sync()
+    t0 = time.perf_counter()
+    for b in solo:
+        b.step(iters, use_graph=False)
+        b.sync()
+    t_solo = time.perf_counter() - t0
+    upd = sum(n * (n - 1) // 2 * 100 for n in ns) * iters
+    return {"problems": count, "n_values": sorted(set(ns)), "iterations_timed": iters,
+            "batched": {"ms_per_iter": t_batch / iters * 1e3, "updates_per_s": upd / t_batch,
+                        "problems_per_s_300_iters": count / (t_batch / iters * 300),
+                        "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]}},
+            "per_problem": {"ms_per_iter_all": t_solo / iters * 1e3, "updates_per_s": upd / t_solo,
+                            "problems_per_s_300_iters": count / (t_solo / iters * 300)},
+            "speedup": t_solo / t_batch}
+
+
 def copy_calibration(mib):
     import torch
     x = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
@@ -112,6 +184,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.serve_sweep:
+        sweep = [serve_trace(r, args.serve_requests, args.serve_precision, seed=k)
+                 for k, r in enumerate([10, 20, 50, 100, 200, 500])]
+        print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
+                          "data": "synthetic", "n_gpus": 1}))
         return
     import torch
     from paper_2011_04240_amd import mato
@@ -166,6 +244,11 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
     }
+    batch.close()
+    if not args.no_serve:
+        out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision)
+    if not args.no_mixed:
+        out["mixed_batching"] = mixed_batching()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds)
     print(json.dumps(out))

@@ -160,6 +160,12 @@ mato_status mato_batch_set_state(mato_batch batch, int32_t q, const void* c,
 /* Linear term g = rho A_fc^T b_fc currently held for problem q, [n][3][n_coef]. */
 mato_status mato_batch_linear_term(mato_batch batch, int32_t q, void* g);
 
+/* Projection of the alpha/beta step for every problem of the batch: 0 projects the
+ * pairwise difference delta onto the spheroid, eq. (sphere_project) (default); 1 projects
+ * delta + lambda/rho, the point the objective of eq. (step_alpha) measures against
+ * (the exact minimiser for spheres).  Takes effect from the next iteration. */
+mato_status mato_batch_set_projection(mato_batch batch, int32_t mode);
+
 /* Pairwise-stage launch shape: pair-instants per workgroup (target) and threads per
  * workgroup (256, 512 or 1024).  mato_batch_autotune times candidate shapes on the
  * batch's own problems before it is used (state is re-initialised afterwards) and
@@ -174,6 +180,67 @@ mato_status mato_batch_autotune(mato_batch batch, int32_t* items_per_wg, int32_t
 mato_status mato_batch_timing(mato_batch batch, int32_t enable);
 mato_status mato_batch_last_times(mato_batch batch, double* total_ms, double* pairwise_ms,
                                   int32_t* pairwise_launches);
+
+/* --------------------------------------------------------------- serving ---
+ * Continuous batching of planning problems with different agent counts.  Requests
+ * wait in arrival order and are admitted while a slot is free and the device-memory
+ * budget (plans + resident problem state) allows; K^{-1} is cached per agent count
+ * (Remarks 1-2) and unused plans are evicted when memory is short.  All resident
+ * problems iterate together (one launch per stage per iteration) and leave when
+ * max ||f_c|| < tol or after max_iters iterations.  A problem's iterates do not
+ * depend on which other problems are resident. */
+typedef struct {
+    int32_t    T;                  /* instants per problem                                 */
+    mato_basis basis;
+    double     a, b, rho;          /* spheroid dimensions l_xy, l_z and the penalty rho    */
+    int32_t    precision;          /* mato_precision                                       */
+    int32_t    max_slots;          /* problems resident at once, >= 1                      */
+    double     hbm_budget_bytes;   /* device bytes for plans and resident problems; <= 0: no limit */
+    int32_t    chunk;              /* iterations per scheduling step, >= 1                 */
+    int32_t    max_iters;          /* iteration cap per problem, >= 1                      */
+    double     tol;                /* convergence threshold on max ||f_c|| (metres)        */
+    int32_t    projection;         /* 0: project delta (eq. (sphere_project)); 1: delta + lambda/rho */
+} mato_server_config;
+
+/* Errors: INVALID_ARG (configuration out of range), OUT_OF_MEMORY, HIP. */
+mato_status mato_server_create(const mato_server_config* cfg, void* hip_stream, mato_server* out);
+void        mato_server_destroy(mato_server s);
+
+/* Builds the plans for n_min..n_max ahead of the requests (OUT_OF_MEMORY if the budget
+ * cannot hold them). */
+mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_max);
+
+/* Queues one problem (n agents; starts/goals [n][3], copied).  *id identifies it.
+ * Errors: INVALID_ARG, UNSUPPORTED (n > MATO_MAX_AGENTS), NONFINITE. */
+mato_status mato_server_submit(mato_server s, int32_t n, const double* starts, const double* goals,
+                               int64_t* id);
+
+/* One scheduling step: retire finished problems, admit queued ones, run `chunk`
+ * iterations of the resident problems (asynchronously).  Reports resident and
+ * queued counts after admission. */
+mato_status mato_server_step(mato_server s, int32_t* running, int32_t* queued);
+
+/* state: 0 queued, 1 resident, 2 finished; iterations taken, converged flag, last
+ * max ||f_c||.  NOT_FOUND for unknown (or already collected) ids. */
+mato_status mato_server_poll(mato_server s, int64_t id, int32_t* state, int32_t* iters,
+                             int32_t* converged, double* r_max);
+
+/* Coefficients [n][3][n_coef] of a finished problem; forgets the request.
+ * NONFINITE if its iteration produced non-finite values. */
+mato_status mato_server_result(mato_server s, int64_t id, double* c);
+
+mato_status mato_server_stats(mato_server s, double* device_bytes, int32_t* n_plans,
+                              int32_t* running, int32_t* queued);
+
+/* Replays an arrival trace in real time: request k (n[k] agents; starts/goals
+ * concatenated as [request][agent][3]) arrives arrival_s[k] seconds after the call
+ * (non-decreasing).  Writes each request's latency (finish - arrival, seconds), its
+ * iterations and convergence flag, and the wall time of the whole trace; results
+ * are not kept. */
+mato_status mato_server_run_trace(mato_server s, int32_t count, const double* arrival_s,
+                                  const int32_t* n, const double* starts, const double* goals,
+                                  double* latency_s, int32_t* iters, int32_t* converged,
+                                  double* wall_s);
 
 /* ------------------------------------------------------ single problem ---
  * Convenience wrappers: a solve is a batch of one (same handle type). */

@@ -14,6 +14,7 @@ Readings of points the paper leaves open (each used below):
     the penalty of eq. (step_x_3d)); Q_x = Pddot^T Pddot as printed in eq. (kkt_step_x);
   * beta = atan2(hypot(dx, dy)/l_xy, dz/l_z), equal to eq. (sphere_project) wherever
     cos(alpha) != 0 and defined where it is 0; delta = 0 exactly gives alpha = beta = 0;
+  * a variant (shifted=True) projects delta + lambda/rho instead of delta;
   * the direction convention of e follows f_c, eq. (sphere_proposed):
     e = (l_xy sin b cos a, l_xy sin b sin a, l_z cos b);
   * d is clipped to d >= 1 as eq. (alpha_beta_constr) states;
@@ -126,8 +127,13 @@ def pair_differences(plan, X):
     return np.transpose(X[plan.I] - X[plan.J], (0, 2, 1))
 
 
-def step_alpha_beta(plan, delta):
-    """Closed-form alpha, beta of eq. (sphere_project) (projection onto the spheroid)."""
+def step_alpha_beta(plan, delta, lam=None, shifted=False):
+    """Closed-form alpha, beta of eq. (sphere_project) (projection onto the spheroid).
+
+    shifted=True is the variant that projects delta + lambda/rho, the point the
+    objective of eq. (step_alpha) actually measures against (exact for spheres)."""
+    if shifted:
+        delta = delta + lam / plan.rho
     dx, dy, dz = delta[..., 0], delta[..., 1], delta[..., 2]
     alpha = np.arctan2(dy, dx)
     beta = np.arctan2(np.hypot(dx, dy) / plan.a, dz / plan.b)
@@ -198,16 +204,17 @@ def smoothness_cost(plan, c):
     return float(np.sum((c @ plan.Pdd.T) ** 2))
 
 
-def iterate_rhs(plan, b_fc, lam, beq):
+def iterate_rhs(plan, b_fc, lam, beq, shifted=False):
     """One pass of the while-loop of Algorithm 1 given b_fc (eq. (b_f)) and lambda^k.
 
     Returns a dict with every intermediate: g, c, nu, X, delta, alpha, beta, d, e,
     proj = d e, f_c, lam (= lambda^{k+1}) and the residual records.
+    shifted selects the projection variant of step_alpha_beta.
     """
     c, nu, g = step_xyz(plan, b_fc, beq)
     X = positions(plan, c)
     delta = pair_differences(plan, X)
-    alpha, beta = step_alpha_beta(plan, delta)
+    alpha, beta = step_alpha_beta(plan, delta, lam, shifted)
     d = step_d(plan, delta, alpha, beta, lam)
     f_c = constraint_residual(plan, delta, alpha, beta, d)
     lam_next = step_lambda(plan, lam, f_c)
@@ -235,10 +242,10 @@ def records(plan, c, nu, g, beq, f_c):
                 cost=smoothness_cost(plan, c), bnd_res=bnd, kkt_res=kkt)
 
 
-def iterate(plan, st):
+def iterate(plan, st, shifted=False):
     """One iteration of Algorithm 1 from State ^k to State ^{k+1}."""
     b_fc = collision_rhs(plan, st.d, st.alpha, st.beta, st.lam)
-    out = iterate_rhs(plan, b_fc, st.lam, st.beq)
+    out = iterate_rhs(plan, b_fc, st.lam, st.beq, shifted)
     nxt = State(c=out["c"], lam=out["lam"], d=out["d"], alpha=out["alpha"], beta=out["beta"],
                 beq=st.beq, nu=out["nu"], g=out["g"], X=out["X"], delta=out["delta"],
                 f_c=out["f_c"], history=st.history)
@@ -247,11 +254,11 @@ def iterate(plan, st):
     return nxt
 
 
-def solve(plan, starts, goals, iters, tol=0.0):
+def solve(plan, starts, goals, iters, tol=0.0, shifted=False):
     """Algorithm 1: initialise, then iterate until `iters` passes or max ||f_c|| < tol."""
     st = initial_state(plan, starts, goals)
     for _ in range(iters):
-        st = iterate(plan, st)
+        st = iterate(plan, st, shifted)
         if st.history["r_max"][-1] < tol:
             break
     return st

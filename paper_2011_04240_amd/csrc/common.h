@@ -19,6 +19,8 @@ constexpr int kNb = 6;          // boundary rows per agent and axis: p, v, a at 
 constexpr int kMaxCoef = 16;
 constexpr int kHistCap = 4096;  // per-problem iteration history kept on the device
 constexpr int kMaxRefine = 4;
+constexpr int kCtrl = 8;        // control words per problem:
+                                // [0] iterations, [1] stopped, [2] non-finite, [3] active, [4] converged
 
 // ---------------------------------------------------------------- errors ---
 void set_error(const char* fmt, ...);
@@ -81,8 +83,10 @@ struct ProblemDesc {
     float* rf;                  // [3][ldq]   r rounded to FP32
     double* part;               // [nslab][4] residual partials: max|f|^2, sum|f|^2
     double* hist;               // [hist_cap][3] r_max, r_rms, cost
-    int* ctrl;                  // [0] iterations, [1] converged, [2] non-finite, [3] active
+    int* ctrl;                  // kCtrl words, see above
     double tol;                 // convergence threshold on r_max (<= 0: none)
+    int iter_cap;               // stop after this many iterations (<= 0: none)
+    int shifted;                // 1: project delta + lambda/rho instead of delta
     // optional parity outputs (nullptr = off)
     S* dbg_proj;                // [T][3][np] d e
     S* dbg_d;                   // [T][np]
@@ -137,11 +141,7 @@ struct mato_plan_s {
     size_t bytes = 0;            // device bytes held
 };
 
-namespace mato {
-template <typename S> struct BatchImpl;
-}
-
 struct mato_batch_s {
     int precision = MATO_FP32;
-    void* impl = nullptr;        // BatchImpl<float> or BatchImpl<double>
+    void* impl = nullptr;        // mato::Engine<float> or mato::Engine<double>
 };

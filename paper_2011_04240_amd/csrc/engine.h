@@ -1,0 +1,734 @@
+// Host engine of libmato: a set of problem slots advanced together, one pass of
+// the while-loop of Algorithm 1 per iteration:
+//
+//   [inverse product]   c = c_eq + K11^{-1} g                     (eq. (kkt_step_x))
+//   [refinement x R]    r = g - H c (FP64);  c += K11^{-1} r
+//   [positions]         X = P c, smoothness cost                  (eq. (param))
+//   [pairwise]          delta; alpha, beta; d; lambda; b_fc; S    (eqs. (sphere_project)-(lag_update), (b_f))
+//   [linear term]       g = rho P^T S = rho A_fc^T b_fc; residual record; convergence test
+//
+// Active slots with the same plan form one group whose right-hand sides are the
+// columns of one matrix-matrix product; all pairwise work of all active slots is
+// one launch over a work list of (slot, block of instants) items.  A fixed batch
+// places every slot in one arena; the server attaches and detaches slots (each
+// with its own device block) between iterations.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "common.h"
+
+namespace mato {
+
+template <typename S>
+hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int, size_t, int, hipStream_t);
+template <typename S>
+hipError_t set_pairwise_lds_limit(size_t);
+template <typename S>
+hipError_t launch_qbuild(const ProblemDesc<S>*, int, int, int, hipStream_t);
+template <typename S>
+hipError_t launch_residual(const ProblemDesc<S>*, int, hipStream_t);
+template <typename S>
+hipError_t launch_positions(const ProblemDesc<S>*, int, int, int, hipStream_t);
+template <typename S>
+hipError_t launch_init(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
+template <typename S>
+hipError_t launch_ceq(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
+hipError_t launch_gemm(int, const GemmTile*, int, const GemmGroup*, const GemmCol*, int, hipStream_t);
+
+inline int device_lds_limit() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
+// Grows a device buffer to hold at least `count` elements (contents are not kept).
+template <typename T>
+inline mato_status ensure_device(T** p, size_t* cap, size_t count) {
+    if (*p && *cap >= count) return MATO_OK;
+    dfree(*p);
+    *p = nullptr;
+    const size_t n = std::max<size_t>(count, 1);
+    if (hipMalloc(p, sizeof(T) * n) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed", sizeof(T) * n);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
+    *cap = n;
+    return MATO_OK;
+}
+
+template <typename S>
+struct Engine {
+    struct Prob {
+        mato_plan plan = nullptr;
+        int n = 0, np = 0, T = 0, nv = 0, ldq = 0, ldc = 0;
+        size_t o_lam = 0, o_ssum = 0, o_X = 0, o_misc = 0, o_c = 0, o_ceq = 0, o_q = 0, o_r = 0, o_qf = 0,
+               o_rf = 0, o_part = 0, o_hist = 0, bytes = 0;
+        char* base = nullptr;        // device block of this slot
+        size_t block = 0;            // bytes of that block (own blocks only)
+        bool own = false;            // the block is the slot's own allocation
+        bool active = false;
+        int nslab = 0;
+        int iter_cap = 0;
+        int shifted = 0;
+        std::vector<double> starts, goals;   // [n][3]
+    };
+
+    int precision = MATO_FP32;
+    int refine = 1;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<Prob> probs;                 // slots
+    char* arena = nullptr;                   // fixed batches: one block for every slot
+    size_t arena_bytes = 0;
+
+    int* dctrl = nullptr;                    // [slots][kCtrl]
+    std::vector<ProblemDesc<S>> hdesc;
+    ProblemDesc<S>* ddesc = nullptr;
+    double** dk0c = nullptr;
+    double** dkinv = nullptr;
+
+    std::vector<WorkItem> hitems;
+    WorkItem* ditems = nullptr;
+    size_t ditems_cap = 0;
+    WorkItem* dscratch = nullptr;            // work items of one slot (initialisation, set-state)
+    size_t dscratch_cap = 0;
+    int items_per_wg = 2048, threads = 256;
+    size_t lds = 0;
+
+    std::vector<GemmGroup> hgroups;
+    std::vector<GemmTile> htiles;
+    GemmGroup* dgroups = nullptr;
+    GemmTile* dtiles = nullptr;
+    GemmCol* dcolsq = nullptr;
+    GemmCol* dcolsr = nullptr;
+    size_t cap_groups = 0, cap_tiles = 0, cap_colsq = 0, cap_colsr = 0;
+    bool lists_dirty = true;
+
+    double tol = 0.0;
+    bool debug = false;
+    S* dbg = nullptr;                        // debug outputs (d e and d) of every slot
+    size_t dbg_bytes = 0;
+
+    hipGraphExec_t g1 = nullptr, gC = nullptr;
+    static constexpr int kChunk = 16;
+
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> pw_events;       // pairs around pairwise launches
+    int pw_used = 0;
+    bool last_timed = false;
+
+    ~Engine() {
+        if (g1) (void)hipGraphExecDestroy(g1);
+        if (gC) (void)hipGraphExecDestroy(gC);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (auto& P : probs)
+            if (P.own) dfree(P.base);
+        dfree(arena);
+        dfree(dctrl);
+        dfree(ddesc);
+        dfree(dk0c);
+        dfree(dkinv);
+        dfree(ditems);
+        dfree(dscratch);
+        dfree(dgroups);
+        dfree(dtiles);
+        dfree(dcolsq);
+        dfree(dcolsr);
+        dfree(dbg);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        for (auto e : pw_events) (void)hipEventDestroy(e);
+    }
+
+    int count() const { return (int)probs.size(); }
+
+    int active_count() const {
+        int k = 0;
+        for (const auto& P : probs) k += P.active;
+        return k;
+    }
+
+    // number of basis coefficients shared by every active slot (0 if they differ)
+    int common_nv() const {
+        int nv = -1;
+        for (const auto& P : probs) {
+            if (!P.active) continue;
+            if (nv < 0) nv = P.nv;
+            if (P.nv != nv) return 0;
+        }
+        return nv < 0 ? 0 : nv;
+    }
+
+    // ------------------------------------------------------------ layout ---
+    static void layout(Prob& P) {
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t off = 0;
+        P.o_lam = off;  off += al(sizeof(S) * (size_t)P.T * 3 * P.np);
+        P.o_ssum = off; off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
+        P.o_X = off;    off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
+        P.o_misc = off; off += al(sizeof(double) * 4);
+        P.o_c = off;    off += al(sizeof(double) * 3 * (size_t)P.ldc);
+        P.o_ceq = off;  off += al(sizeof(double) * 3 * (size_t)P.ldc);
+        P.o_q = off;    off += al(sizeof(double) * 3 * (size_t)P.ldq);
+        P.o_r = off;    off += al(sizeof(double) * 3 * (size_t)P.ldq);
+        P.o_qf = off;   off += al(sizeof(float) * 3 * (size_t)P.ldq);
+        P.o_rf = off;   off += al(sizeof(float) * 3 * (size_t)P.ldq);
+        P.o_part = off; off += al(sizeof(double) * 4 * (size_t)P.T);   // at most T slabs
+        P.o_hist = off; off += al(sizeof(double) * 3 * kHistCap);
+        P.bytes = off;
+    }
+
+    static void describe(Prob& P, mato_plan plan) {
+        P.plan = plan;
+        P.n = plan->n;
+        P.np = P.n * (P.n - 1) / 2;
+        P.T = plan->T;
+        P.nv = plan->nv;
+        P.ldq = round_up(P.n * (P.nv + kNb), 32);   // >= the operand stride ldk = round_up(11n, 32)
+        P.ldc = P.n * P.nv;
+        layout(P);
+    }
+
+    static size_t slot_bytes(mato_plan plan) {
+        Prob P;
+        describe(P, plan);
+        return P.bytes;
+    }
+
+    // Control words, descriptors and per-slot pointer tables for `cap` slots.
+    mato_status init_capacity(int cap) {
+        probs.resize(cap);
+        hdesc.assign(cap, ProblemDesc<S>());
+        MATO_HIP(hipMalloc(&dctrl, sizeof(int) * kCtrl * cap));
+        MATO_HIP(hipMemset(dctrl, 0, sizeof(int) * kCtrl * cap));
+        MATO_HIP(hipMalloc(&ddesc, sizeof(ProblemDesc<S>) * cap));
+        MATO_HIP(hipMalloc(&dk0c, sizeof(double*) * cap));
+        MATO_HIP(hipMalloc(&dkinv, sizeof(double*) * cap));
+        MATO_HIP(hipMemset(dk0c, 0, sizeof(double*) * cap));
+        MATO_HIP(hipMemset(dkinv, 0, sizeof(double*) * cap));
+        if (!ev0) MATO_HIP(hipEventCreate(&ev0));
+        if (!ev1) MATO_HIP(hipEventCreate(&ev1));
+        return MATO_OK;
+    }
+
+    void fill_desc(int q) {
+        const Prob& P = probs[q];
+        ProblemDesc<S>& D = hdesc[q];
+        memset(&D, 0, sizeof(D));
+        D.ctrl = dctrl + kCtrl * q;
+        if (!P.plan || !P.base) return;
+        const mato_plan pl = P.plan;
+        char* b = P.base;
+        D.n = P.n; D.np = P.np; D.T = P.T; D.nv = P.nv; D.ldq = P.ldq; D.ldc = P.ldc;
+        D.nslab = P.nslab; D.hist_cap = kHistCap;
+        D.a = pl->a; D.b = pl->b; D.rho = pl->rho;
+        D.ia2 = (S)(1.0 / (pl->a * pl->a));
+        D.ib2 = (S)(1.0 / (pl->b * pl->b));
+        D.lz = (S)pl->b;
+        D.srho = (S)pl->rho;
+        D.sirho = (S)(1.0 / pl->rho);
+        D.P = pl->dP; D.Pdd = pl->dPdd; D.PtP = pl->dPtP; D.PddtPdd = pl->dPddtPdd; D.A = pl->dA;
+        D.pairs = pl->dPairs;
+        D.lam = (S*)(b + P.o_lam);
+        D.ssum = (S*)(b + P.o_ssum);
+        D.X = (S*)(b + P.o_X);
+        D.misc = (double*)(b + P.o_misc);
+        D.c = (double*)(b + P.o_c);
+        D.ceq = (double*)(b + P.o_ceq);
+        D.q = (double*)(b + P.o_q);
+        D.r = (double*)(b + P.o_r);
+        D.qf = (float*)(b + P.o_qf);
+        D.rf = (float*)(b + P.o_rf);
+        D.part = (double*)(b + P.o_part);
+        D.hist = (double*)(b + P.o_hist);
+        D.tol = tol;
+        D.iter_cap = P.iter_cap;
+        D.shifted = P.shifted;
+        if (debug && dbg) {
+            size_t off = 0;
+            for (int k = 0; k < q; ++k) off += (size_t)probs[k].T * 4 * probs[k].np;
+            D.dbg_proj = dbg + off;
+            D.dbg_d = dbg + off + (size_t)P.T * 3 * P.np;
+        }
+    }
+
+    mato_status upload_desc() {
+        for (int q = 0; q < count(); ++q) fill_desc(q);
+        MATO_HIP(hipMemcpyAsync(ddesc, hdesc.data(), sizeof(ProblemDesc<S>) * count(), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        return MATO_OK;
+    }
+
+    // work items of slot q: instants in blocks of tc
+    void slot_items(int q, std::vector<WorkItem>& out, size_t* maxlds, int as_prob) {
+        Prob& P = probs[q];
+        const int cap = device_lds_limit() - 1024;   // room for the kernel's static reduction buffer
+        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S);
+        int tc = std::max(1, items_per_wg / std::max(1, P.np));
+        tc = std::min(tc, P.T);
+        while (tc > 1 && per_t * tc > (size_t)cap) --tc;
+        *maxlds = std::max(*maxlds, per_t * tc);
+        P.nslab = (P.T + tc - 1) / tc;
+        for (int s = 0; s < P.nslab; ++s) {
+            WorkItem w;
+            w.prob = as_prob;
+            w.t0 = s * tc;
+            w.tc = std::min(tc, P.T - w.t0);
+            w.slab = s;
+            out.push_back(w);
+        }
+    }
+
+    mato_status check_lds(const Prob& P) const {
+        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S);
+        if (per_t > (size_t)(device_lds_limit() - 1024)) {
+            set_error("n = %d needs %zu bytes of LDS per instant, device allows %d", P.n, per_t,
+                      device_lds_limit() - 1024);
+            return MATO_ERR_UNSUPPORTED;
+        }
+        return MATO_OK;
+    }
+
+    // Work list, product groups and tiles of the active slots.
+    mato_status rebuild_lists() {
+        hitems.clear();
+        size_t maxlds = 0;
+        for (int q = 0; q < count(); ++q)
+            if (probs[q].active) slot_items(q, hitems, &maxlds, q);
+        lds = maxlds;
+        MATO_TRY(ensure_device(&ditems, &ditems_cap, hitems.size()));
+        if (!hitems.empty())
+            MATO_HIP(hipMemcpy(ditems, hitems.data(), sizeof(WorkItem) * hitems.size(), hipMemcpyHostToDevice));
+        if (lds > 0 && set_pairwise_lds_limit<S>(lds) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot raise the LDS limit of the pairwise kernel to %zu bytes", lds);
+            return MATO_ERR_UNSUPPORTED;
+        }
+        std::map<mato_plan, std::vector<int>> members;
+        std::vector<mato_plan> order;
+        for (int q = 0; q < count(); ++q) {
+            if (!probs[q].active) continue;
+            if (!members.count(probs[q].plan)) order.push_back(probs[q].plan);
+            members[probs[q].plan].push_back(q);
+        }
+        std::vector<GemmCol> colq, colr;
+        hgroups.clear();
+        htiles.clear();
+        for (size_t g = 0; g < order.size(); ++g) {
+            const mato_plan pl = order[g];
+            const auto& mem = members[pl];
+            GemmGroup G;
+            G.Ahi = pl->dAhi;
+            G.Alo = pl->dAlo;
+            G.M = pl->n * pl->nv;
+            G.K = pl->n * pl->nv;
+            G.ldk = pl->ldk;
+            G.ncols = 3 * (int)mem.size();
+            G.first_col = (int)colq.size();
+            for (int q : mem)
+                for (int a = 0; a < 3; ++a) {
+                    const Prob& P = probs[q];
+                    GemmCol cq, cr;
+                    cq.c = cr.c = (double*)(P.base + P.o_c) + (size_t)a * P.ldc;
+                    cq.ceq = cr.ceq = (const double*)(P.base + P.o_ceq) + (size_t)a * P.ldc;
+                    cq.b = (const double*)(P.base + P.o_q) + (size_t)a * P.ldq;
+                    cr.b = (const double*)(P.base + P.o_r) + (size_t)a * P.ldq;
+                    cq.bf = (const float*)(P.base + P.o_qf) + (size_t)a * P.ldq;
+                    cr.bf = (const float*)(P.base + P.o_rf) + (size_t)a * P.ldq;
+                    cq.ctrl = cr.ctrl = dctrl + kCtrl * q;
+                    colq.push_back(cq);
+                    colr.push_back(cr);
+                }
+            hgroups.push_back(G);
+            const int Mp = round_up(G.M, 64);
+            for (int c0 = 0; c0 < G.ncols; c0 += 64)
+                for (int m0 = 0; m0 < Mp; m0 += 64) htiles.push_back(GemmTile{(int)g, m0, c0, 0});
+        }
+        MATO_TRY(ensure_device(&dgroups, &cap_groups, hgroups.size()));
+        MATO_TRY(ensure_device(&dtiles, &cap_tiles, htiles.size()));
+        MATO_TRY(ensure_device(&dcolsq, &cap_colsq, colq.size()));
+        MATO_TRY(ensure_device(&dcolsr, &cap_colsr, colr.size()));
+        if (!hgroups.empty()) {
+            MATO_HIP(hipMemcpy(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size(), hipMemcpyHostToDevice));
+            MATO_HIP(hipMemcpy(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size(), hipMemcpyHostToDevice));
+            MATO_HIP(hipMemcpy(dcolsq, colq.data(), sizeof(GemmCol) * colq.size(), hipMemcpyHostToDevice));
+            MATO_HIP(hipMemcpy(dcolsr, colr.data(), sizeof(GemmCol) * colr.size(), hipMemcpyHostToDevice));
+        }
+        MATO_TRY(upload_desc());          // slab counts may have changed
+        drop_graphs();
+        lists_dirty = false;
+        return MATO_OK;
+    }
+
+    // --------------------------------------------------------- slots ---
+    // Binds slot q to a problem: device block (arena part or own, reused when large
+    // enough), boundary data, control words, descriptor.  Does not initialise.
+    mato_status attach(int q, mato_plan plan, const double* starts, const double* goals, char* arena_part) {
+        Prob& P = probs[q];
+        describe(P, plan);
+        MATO_TRY(check_lds(P));
+        if (arena_part) {
+            if (P.own) dfree(P.base);
+            P.own = false;
+            P.base = arena_part;
+        } else {
+            if (!P.own || P.block < P.bytes) {
+                if (P.own) dfree(P.base);
+                P.base = nullptr;
+                P.own = false;
+                if (hipMalloc(&P.base, P.bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    P.base = nullptr;
+                    set_error("device allocation of %zu bytes failed", P.bytes);
+                    return MATO_ERR_OUT_OF_MEMORY;
+                }
+                P.own = true;
+                P.block = P.bytes;
+            }
+            MATO_HIP(hipMemsetAsync(P.base, 0, P.bytes, stream));
+        }
+        P.starts.assign(starts, starts + 3 * (size_t)P.n);
+        P.goals.assign(goals, goals + 3 * (size_t)P.n);
+        for (size_t k = 0; k < P.starts.size(); ++k)
+            if (!std::isfinite(P.starts[k]) || !std::isfinite(P.goals[k])) {
+                set_error("non-finite start or goal");
+                return MATO_ERR_NONFINITE;
+            }
+        P.active = true;
+        double* k0 = plan->dK0c;
+        double* ki = plan->dKinv;
+        MATO_HIP(hipMemcpyAsync(dk0c + q, &k0, sizeof(double*), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipMemcpyAsync(dkinv + q, &ki, sizeof(double*), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        lists_dirty = true;
+        return MATO_OK;
+    }
+
+    // Marks slot q inactive; its block is kept for reuse.
+    mato_status detach(int q) {
+        Prob& P = probs[q];
+        if (!P.active) return MATO_OK;
+        P.active = false;
+        int z[kCtrl] = {0};
+        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, z, sizeof(z), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        lists_dirty = true;
+        return MATO_OK;
+    }
+
+    // Releases the device block of an inactive slot.
+    void release_block(int q) {
+        Prob& P = probs[q];
+        if (P.active || !P.own) return;
+        dfree(P.base);
+        P.base = nullptr;
+        P.own = false;
+        P.block = 0;
+        P.plan = nullptr;
+    }
+
+    // Boundary rows of q: [start, 0, 0, goal, 0, 0] per agent and axis, FP64 and FP32.
+    mato_status upload_beq(int q) {
+        const Prob& P = probs[q];
+        std::vector<double> hq((size_t)3 * P.ldq, 0.0);
+        for (int a = 0; a < 3; ++a)
+            for (int i = 0; i < P.n; ++i) {
+                double* b = &hq[(size_t)a * P.ldq + (size_t)P.n * P.nv + (size_t)i * kNb];
+                b[0] = P.starts[(size_t)i * 3 + a];
+                b[3] = P.goals[(size_t)i * 3 + a];
+            }
+        std::vector<float> hf(hq.begin(), hq.end());
+        MATO_HIP(hipMemcpyAsync(P.base + P.o_q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipMemcpyAsync(P.base + P.o_qf, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        return MATO_OK;
+    }
+
+    mato_status reset_ctrl(int q) {
+        int w[kCtrl] = {0};
+        w[3] = 1;
+        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, w, sizeof(w), hipMemcpyHostToDevice, stream));
+        return MATO_OK;
+    }
+
+    // Initialisation of Algorithm 1 for every active slot (fixed batches).
+    mato_status enqueue_init_all() {
+        if (lists_dirty) MATO_TRY(rebuild_lists());
+        for (int q = 0; q < count(); ++q)
+            if (probs[q].active) {
+                MATO_TRY(reset_ctrl(q));
+                MATO_TRY(upload_beq(q));
+            }
+        const int nv = common_nv();
+        MATO_HIP(launch_init<S>(ddesc, dk0c, count(), stream));
+        MATO_HIP(launch_ceq<S>(ddesc, dkinv, count(), stream));
+        MATO_HIP(launch_positions<S>(ddesc, count(), kModeInit, nv, stream));
+        MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, nv, stream));
+        MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, nv, stream));
+        return MATO_OK;
+    }
+
+    // Initialisation of one slot (server admission): kernels launched on that slot only.
+    mato_status enqueue_init_one(int q) {
+        if (lists_dirty) MATO_TRY(rebuild_lists());
+        MATO_TRY(reset_ctrl(q));
+        MATO_TRY(upload_beq(q));
+        std::vector<WorkItem> items;
+        size_t l = 0;
+        slot_items(q, items, &l, 0);
+        MATO_TRY(ensure_device(&dscratch, &dscratch_cap, items.size()));
+        MATO_HIP(hipMemcpyAsync(dscratch, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        const int nv = probs[q].nv == 11 ? 11 : 0;
+        const ProblemDesc<S>* d = ddesc + q;
+        MATO_HIP(launch_init<S>(d, dk0c + q, 1, stream));
+        MATO_HIP(launch_ceq<S>(d, dkinv + q, 1, stream));
+        MATO_HIP(launch_positions<S>(d, 1, kModeInit, nv, stream));
+        MATO_HIP(launch_pairwise<S>(dscratch, (int)items.size(), d, kModeInit, threads, std::max(l, lds), nv, stream));
+        MATO_HIP(launch_qbuild<S>(d, 1, kModeInit, nv, stream));
+        return MATO_OK;
+    }
+
+    // --------------------------------------------------------- iterations ---
+    hipError_t enqueue_iteration(hipStream_t st, bool events) {
+        const int nv = common_nv();
+        hipError_t e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsq, 0, st);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < refine; ++k) {
+            e = launch_residual<S>(ddesc, count(), st);
+            if (e != hipSuccess) return e;
+            e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);
+        if (e != hipSuccess) return e;
+        if (events) {
+            while ((int)pw_events.size() < pw_used + 2) {
+                hipEvent_t ev;
+                e = hipEventCreate(&ev);
+                if (e != hipSuccess) return e;
+                pw_events.push_back(ev);
+            }
+            e = hipEventRecord(pw_events[pw_used], st);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, st);
+        if (e != hipSuccess) return e;
+        if (events) {
+            e = hipEventRecord(pw_events[pw_used + 1], st);
+            if (e != hipSuccess) return e;
+            pw_used += 2;
+        }
+        return launch_qbuild<S>(ddesc, count(), kModeIter, nv, st);
+    }
+
+    void drop_graphs() {
+        if (g1) (void)hipGraphExecDestroy(g1);
+        if (gC) (void)hipGraphExecDestroy(gC);
+        g1 = gC = nullptr;
+    }
+
+    mato_status capture(int iters, hipGraphExec_t* out) {
+        if (!cap_stream) MATO_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        MATO_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < iters && e == hipSuccess; ++k) e = enqueue_iteration(cap_stream, false);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            return MATO_ERR_HIP;
+        }
+        e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            set_error("graph instantiation failed: %s", hipGetErrorString(e));
+            return MATO_ERR_HIP;
+        }
+        return MATO_OK;
+    }
+
+    mato_status set_tol(double new_tol) {
+        if (new_tol != tol) {
+            tol = new_tol;
+            MATO_TRY(upload_desc());
+        }
+        return MATO_OK;
+    }
+
+    mato_status step(int k, double new_tol, bool use_graph) {
+        if (k < 0) { set_error("negative iteration count"); return MATO_ERR_INVALID_ARG; }
+        MATO_TRY(set_tol(new_tol));
+        if (lists_dirty) MATO_TRY(rebuild_lists());
+        pw_used = 0;
+        last_timed = timing;
+        const bool per_kernel_events = timing && !use_graph;
+        if (timing) MATO_HIP(hipEventRecord(ev0, stream));
+        if (active_count() > 0) {
+            if (use_graph && k > 0) {
+                if (!gC && k >= kChunk) MATO_TRY(capture(kChunk, &gC));
+                if (!g1) MATO_TRY(capture(1, &g1));
+                int left = k;
+                while (left >= kChunk) {
+                    MATO_HIP(hipGraphLaunch(gC, stream));
+                    left -= kChunk;
+                }
+                while (left-- > 0) MATO_HIP(hipGraphLaunch(g1, stream));
+            } else {
+                for (int i = 0; i < k; ++i) MATO_HIP(enqueue_iteration(stream, per_kernel_events));
+            }
+        }
+        if (timing) MATO_HIP(hipEventRecord(ev1, stream));
+        return MATO_OK;
+    }
+
+    mato_status read_ctrl(std::vector<int>& ctrl) {
+        ctrl.resize((size_t)kCtrl * count());
+        MATO_HIP(hipMemcpyAsync(ctrl.data(), dctrl, sizeof(int) * ctrl.size(), hipMemcpyDeviceToHost, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        return MATO_OK;
+    }
+
+    mato_status run(int iters, double new_tol, int check_every) {
+        if (iters < 0 || check_every < 1) { set_error("iters must be >= 0 and check_every >= 1"); return MATO_ERR_INVALID_ARG; }
+        int done = 0;
+        std::vector<int> ctrl;
+        while (done < iters) {
+            const int k = std::min(check_every, iters - done);
+            MATO_TRY(step(k, new_tol, true));
+            done += k;
+            MATO_TRY(read_ctrl(ctrl));
+            bool all = true;
+            for (int q = 0; q < count(); ++q)
+                if (probs[q].active) all = all && ctrl[kCtrl * q + 1];
+            if (all) break;
+        }
+        MATO_TRY(read_ctrl(ctrl));
+        bool nonfinite = false, pending = false;
+        for (int q = 0; q < count(); ++q) {
+            if (!probs[q].active) continue;
+            nonfinite = nonfinite || ctrl[kCtrl * q + 2];
+            pending = pending || !ctrl[kCtrl * q + 4];
+        }
+        if (nonfinite) { set_error("non-finite values in the iteration"); return MATO_ERR_NONFINITE; }
+        if (pending && new_tol > 0) return MATO_WARN_NOT_CONVERGED;
+        return MATO_OK;
+    }
+
+    mato_status set_tiles(int ipw, int thr) {
+        if (ipw < 1 || (thr != 256 && thr != 512 && thr != 1024)) {
+            set_error("items_per_wg must be >= 1 and threads one of 256, 512, 1024");
+            return MATO_ERR_INVALID_ARG;
+        }
+        MATO_HIP(hipStreamSynchronize(stream));
+        items_per_wg = ipw;
+        threads = thr;
+        return rebuild_lists();
+    }
+
+    std::string tune_key() const {
+        hipDeviceProp_t prop;
+        int dev = 0;
+        std::string arch = "gfx";
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+        std::vector<int> ns;
+        int T = 0;
+        for (auto& P : probs)
+            if (P.active) {
+                ns.push_back(P.n);
+                T = P.T;
+            }
+        std::sort(ns.begin(), ns.end());
+        uint64_t h = 1469598103934665603ull;
+        for (int v : ns) h = (h ^ (uint64_t)v) * 1099511628211ull;
+        std::ostringstream o;
+        o << arch.substr(0, arch.find(':')) << "|prec=" << precision << "|T=" << T << "|count=" << ns.size()
+          << "|ns=" << std::hex << h;
+        return o.str();
+    }
+
+    // Times the pairwise launch for candidate shapes on this batch's problems, keeps
+    // the fastest and re-initialises the state (the timing runs overwrite it).
+    mato_status autotune(int* ipw_out, int* thr_out) {
+        const char* path = getenv("MATO_TUNE_CACHE");
+        const std::string key = tune_key();
+        if (path) {
+            std::ifstream f(path);
+            std::string k;
+            int ipw, thr;
+            while (f >> k >> ipw >> thr)
+                if (k == key) {
+                    MATO_TRY(set_tiles(ipw, thr));
+                    if (ipw_out) *ipw_out = ipw;
+                    if (thr_out) *thr_out = thr;
+                    return MATO_OK;
+                }
+        }
+        const int ipws[] = {512, 1024, 2048, 4096, 8192, 16384};
+        const int thrs[] = {256, 512, 1024};
+        float best = 1e30f;
+        int bi = items_per_wg, bt = threads;
+        hipEvent_t e0, e1;
+        MATO_HIP(hipEventCreate(&e0));
+        MATO_HIP(hipEventCreate(&e1));
+        const int nv = common_nv();
+        for (int ipw : ipws)
+            for (int thr : thrs) {
+                if (set_tiles(ipw, thr) != MATO_OK) continue;
+                MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, stream));
+                MATO_HIP(hipEventRecord(e0, stream));
+                const int reps = 5;
+                for (int r = 0; r < reps; ++r)
+                    MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, stream));
+                MATO_HIP(hipEventRecord(e1, stream));
+                MATO_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; bi = ipw; bt = thr; }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        MATO_TRY(set_tiles(bi, bt));
+        MATO_TRY(enqueue_init_all());
+        MATO_HIP(hipStreamSynchronize(stream));
+        if (path) {
+            std::ofstream f(path, std::ios::app);
+            f << key << " " << bi << " " << bt << "\n";
+        }
+        if (ipw_out) *ipw_out = bi;
+        if (thr_out) *thr_out = bt;
+        return MATO_OK;
+    }
+
+    mato_status enable_debug(bool on) {
+        MATO_HIP(hipStreamSynchronize(stream));
+        if (on && !dbg) {
+            size_t elems = 0;
+            for (auto& P : probs) elems += (size_t)P.T * 4 * (size_t)P.np;
+            dbg_bytes = sizeof(S) * std::max<size_t>(elems, 1);
+            MATO_HIP(hipMalloc(&dbg, dbg_bytes));
+            MATO_HIP(hipMemset(dbg, 0, dbg_bytes));
+        }
+        debug = on;
+        return upload_desc();
+    }
+};
+
+}  // namespace mato

@@ -21,7 +21,8 @@
 //     d* = e^T (delta + lambda/rho) / ||e||^2 = s (1 + delta^T lambda / (rho ||delta||^2)),
 //     d e = w delta with w = d / s = max(1/s, 1 + delta^T lambda / (rho ||delta||^2)),
 //     f_c = delta - d e.
-// delta = 0 takes alpha = beta = 0, i.e. e = (0, 0, l_z).
+// delta = 0 takes alpha = beta = 0, i.e. e = (0, 0, l_z).  A per-problem variant
+// projects v = delta + lambda/rho instead (e = v / s_v, d = max(1, s_v)).
 //
 // Descriptor fields are read into registers once per workgroup and device
 // pointers are used in the global address space, so that stores cannot force
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     S* const dbg_d_p = Dp->dbg_d;
     gptr<double> part = glob(Dp->part);
     const S ia2 = Dp->ia2, ib2 = Dp->ib2, rho = Dp->srho, irho = Dp->sirho, lzl = Dp->lz;
+    const bool shifted = Dp->shifted != 0;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S* Xs = reinterpret_cast<S*>(smem_raw);
@@ -194,22 +196,41 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const S dx = X[i] - X[j];
             const S dy = X[n + i] - X[n + j];
             const S dz = X[2 * n + i] - X[2 * n + j];
-            const S q2 = (dx * dx + dy * dy) * ia2 + dz * dz * ib2;   // s^2
             S px, py, pz, dd;
-            if (q2 > 0) {
-                const S D2 = dx * dx + dy * dy + dz * dz;
-                const S rs = Recip<S>::rsq(q2);                     // 1 / s
-                const S dl = dx * lx + dy * ly + dz * lzm;
-                const S w = fmax(rs, S(1) + dl * irho * Recip<S>::rcp(D2));
-                px = w * dx;
-                py = w * dy;
-                pz = w * dz;
-                dd = w * (q2 * rs);                                 // d = w s
-            } else {                                                // delta = 0: e = (0, 0, l_z)
-                dd = fmax(S(1), lzm * irho / lzl);
-                px = 0;
-                py = 0;
-                pz = dd * lzl;
+            if (!shifted) {
+                const S q2 = (dx * dx + dy * dy) * ia2 + dz * dz * ib2;   // s^2
+                if (q2 > 0) {
+                    const S D2 = dx * dx + dy * dy + dz * dz;
+                    const S rs = Recip<S>::rsq(q2);                     // 1 / s
+                    const S dl = dx * lx + dy * ly + dz * lzm;
+                    const S w = fmax(rs, S(1) + dl * irho * Recip<S>::rcp(D2));
+                    px = w * dx;
+                    py = w * dy;
+                    pz = w * dz;
+                    dd = w * (q2 * rs);                                 // d = w s
+                } else {                                                // delta = 0: e = (0, 0, l_z)
+                    dd = fmax(S(1), lzm * irho / lzl);
+                    px = 0;
+                    py = 0;
+                    pz = dd * lzl;
+                }
+            } else {
+                // variant: project v = delta + lambda/rho; then d = max(1, s_v), d e = max(1/s_v, 1) v
+                const S vx = dx + lx * irho, vy = dy + ly * irho, vz = dz + lzm * irho;
+                const S q2 = (vx * vx + vy * vy) * ia2 + vz * vz * ib2;
+                if (q2 > 0) {
+                    const S rs = Recip<S>::rsq(q2);
+                    const S w = fmax(rs, S(1));
+                    px = w * vx;
+                    py = w * vy;
+                    pz = w * vz;
+                    dd = w * (q2 * rs);
+                } else {                                                // v = 0: e = (0, 0, l_z), d = 1
+                    dd = S(1);
+                    px = 0;
+                    py = 0;
+                    pz = lzl;
+                }
             }
             const S fx = dx - px, fy = dy - py, fz = dz - pz;
             S nlx = 0, nly = 0, nlz = 0;
@@ -410,6 +431,9 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
             ctrl[2] = 1;
             ctrl[1] = 1;
         } else if (Dp->tol > 0.0 && rmax < Dp->tol) {
+            ctrl[4] = 1;
+            ctrl[1] = 1;
+        } else if (Dp->iter_cap > 0 && itn + 1 >= Dp->iter_cap) {
             ctrl[1] = 1;
         }
     }

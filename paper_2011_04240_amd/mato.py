@@ -40,6 +40,13 @@ class _Basis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_coef", ctypes.c_int32), ("t_final", ctypes.c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("basis", _Basis), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("rho", ctypes.c_double), ("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_double), ("chunk", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("projection", ctypes.c_int32)]
+
+
 _lib = None
 _vp, _i32, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
 _pi32, _pf64, _pvp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)
@@ -64,11 +71,21 @@ SIGNATURES = {
     "mato_batch_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mato_batch_set_state": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "mato_batch_linear_term": (_i32, [_vp, _i32, _vp]),
+    "mato_batch_set_projection": (_i32, [_vp, _i32]),
     "mato_batch_set_tiles": (_i32, [_vp, _i32, _i32]),
     "mato_batch_get_tiles": (_i32, [_vp, _pi32, _pi32]),
     "mato_batch_autotune": (_i32, [_vp, _pi32, _pi32]),
     "mato_batch_timing": (_i32, [_vp, _i32]),
     "mato_batch_last_times": (_i32, [_vp, _pf64, _pf64, _pi32]),
+    "mato_server_create": (_i32, [ctypes.POINTER(ServerConfig), _vp, _pvp]),
+    "mato_server_destroy": (None, [_vp]),
+    "mato_server_warm": (_i32, [_vp, _i32, _i32]),
+    "mato_server_submit": (_i32, [_vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "mato_server_step": (_i32, [_vp, _pi32, _pi32]),
+    "mato_server_poll": (_i32, [_vp, ctypes.c_int64, _pi32, _pi32, _pi32, _pf64]),
+    "mato_server_result": (_i32, [_vp, ctypes.c_int64, _vp]),
+    "mato_server_stats": (_i32, [_vp, _pf64, _pi32, _pi32, _pi32]),
+    "mato_server_run_trace": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _pf64]),
     "mato_solve_run": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _pvp]),
     "mato_solve_coeffs": (_i32, [_vp, _vp]),
     "mato_residuals": (_i32, [_vp, _vp, _vp, _vp, _i32, _pi32]),
@@ -204,6 +221,10 @@ def mato_batch_linear_term(batch, q, out):
     _check(lib().mato_batch_linear_term(batch, q, _ptr(out)))
 
 
+def mato_batch_set_projection(batch, mode):
+    _check(lib().mato_batch_set_projection(batch, mode))
+
+
 def mato_batch_set_tiles(batch, items_per_wg, threads):
     _check(lib().mato_batch_set_tiles(batch, items_per_wg, threads))
 
@@ -228,6 +249,56 @@ def mato_batch_last_times(batch):
     t, p, n = _f64(), _f64(), _i32()
     _check(lib().mato_batch_last_times(batch, ctypes.byref(t), ctypes.byref(p), ctypes.byref(n)))
     return t.value, p.value, n.value
+
+
+def mato_server_create(cfg, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().mato_server_create(ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
+    return h
+
+
+def mato_server_destroy(server):
+    lib().mato_server_destroy(server)
+
+
+def mato_server_warm(server, n_min, n_max):
+    _check(lib().mato_server_warm(server, n_min, n_max))
+
+
+def mato_server_submit(server, n, starts, goals):
+    i = ctypes.c_int64()
+    _check(lib().mato_server_submit(server, n, _ptr(starts), _ptr(goals), ctypes.byref(i)))
+    return i.value
+
+
+def mato_server_step(server):
+    r, q = _i32(), _i32()
+    _check(lib().mato_server_step(server, ctypes.byref(r), ctypes.byref(q)))
+    return r.value, q.value
+
+
+def mato_server_poll(server, req):
+    st, it, cv = _i32(), _i32(), _i32()
+    rm = _f64()
+    _check(lib().mato_server_poll(server, req, ctypes.byref(st), ctypes.byref(it), ctypes.byref(cv), ctypes.byref(rm)))
+    return st.value, it.value, bool(cv.value), rm.value
+
+
+def mato_server_result(server, req, out):
+    _check(lib().mato_server_result(server, req, _ptr(out)))
+
+
+def mato_server_stats(server):
+    b, p, r, q = _f64(), _i32(), _i32(), _i32()
+    _check(lib().mato_server_stats(server, ctypes.byref(b), ctypes.byref(p), ctypes.byref(r), ctypes.byref(q)))
+    return b.value, p.value, r.value, q.value
+
+
+def mato_server_run_trace(server, arrival_s, ns, starts, goals, latency, iters, converged):
+    wall = _f64()
+    _check(lib().mato_server_run_trace(server, len(ns), _ptr(arrival_s), _ptr(ns), _ptr(starts), _ptr(goals),
+                                       _ptr(latency), _ptr(iters), _ptr(converged), ctypes.byref(wall)))
+    return wall.value
 
 
 # ---------------------------------------------------------------- owners ---
@@ -256,6 +327,62 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             mato_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (problems of any agent count up to MATO_MAX_AGENTS)."""
+
+    def __init__(self, T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", max_slots=64,
+                 hbm_budget_bytes=0.0, chunk=10, max_iters=2000, tol=1e-3, shifted=False, stream=None):
+        self.T, self.n_coef = T, n_coef
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cfg = ServerConfig(T, _Basis(0, n_coef, t_final), a, b, rho, self.precision, max_slots, hbm_budget_bytes,
+                           chunk, max_iters, tol, int(bool(shifted)))
+        self.handle = mato_server_create(cfg, stream)
+
+    def warm(self, n_min, n_max):
+        mato_server_warm(self.handle, n_min, n_max)
+
+    def submit(self, starts, goals):
+        starts = np.ascontiguousarray(starts, np.float64)
+        goals = np.ascontiguousarray(goals, np.float64)
+        return mato_server_submit(self.handle, starts.shape[0], starts, goals)
+
+    def step(self):
+        return mato_server_step(self.handle)
+
+    def poll(self, req):
+        return mato_server_poll(self.handle, req)
+
+    def result(self, req, n):
+        out = np.empty((n, 3, self.n_coef), np.float64)
+        mato_server_result(self.handle, req, out)
+        return out
+
+    def stats(self):
+        return mato_server_stats(self.handle)
+
+    def run_trace(self, arrival_s, starts_list, goals_list):
+        ns = np.ascontiguousarray([np.asarray(s).shape[0] for s in starts_list], np.int32)
+        arr = np.ascontiguousarray(arrival_s, np.float64)
+        starts = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64).reshape(-1, 3) for s in starts_list]))
+        goals = np.ascontiguousarray(np.concatenate([np.asarray(g, np.float64).reshape(-1, 3) for g in goals_list]))
+        lat = np.zeros(len(ns))
+        its = np.zeros(len(ns), np.int32)
+        conv = np.zeros(len(ns), np.int32)
+        wall = mato_server_run_trace(self.handle, arr, ns, starts, goals, lat, its, conv)
+        return lat, its, conv, wall
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mato_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -334,6 +461,9 @@ class Batch:
         out = np.empty((p.n, 3, p.n_coef), np.float64)
         mato_batch_linear_term(self.handle, q, out)
         return out
+
+    def set_projection(self, shifted):
+        mato_batch_set_projection(self.handle, int(bool(shifted)))
 
     def set_tiles(self, items_per_wg, threads):
         mato_batch_set_tiles(self.handle, items_per_wg, threads)

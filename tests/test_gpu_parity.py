@@ -74,23 +74,25 @@ def test_initial_state_matches_oracle(precision):
     assert rel(b.linear_term(0), g_ref) < tol
 
 
-def _single_step(name, precision, k_oracle=5):
+def _single_step(name, precision, k_oracle=5, shifted=False):
     c = CASES[name]
     s, g = c["gen"]()
     op = _oracle_plan(c)
     st = am.initial_state(op, s, g)
     for _ in range(k_oracle):
-        st = am.iterate(op, st)
+        st = am.iterate(op, st, shifted)
     S = np.float64 if precision == "fp64" else np.float32
     lam = st.lam.astype(S)
     proj = st.proj(op).astype(S)
     b_fc = proj.astype(np.float64) - lam.astype(np.float64) / op.rho
-    ref = am.iterate_rhs(op, b_fc, lam.astype(np.float64), st.beq)
+    ref = am.iterate_rhs(op, b_fc, lam.astype(np.float64), st.beq, shifted)
     g_next = am.linear_term(op, ref["proj"] - ref["lam"] / op.rho)
 
     gp = _gpu_plan(c, precision)
     bt = mato.Batch([gp], [s], [g])
     bt.set_state(0, st.c, lam, proj)
+    if shifted:
+        bt.set_projection(True)
     assert rel(bt.linear_term(0), ref["g"]) < (1e-10 if precision == "fp64" else 1e-5)
     bt.debug(True)
     bt.step(1, use_graph=False)
@@ -114,6 +116,31 @@ def test_single_step_parity(name, precision):
     tol = 1e-8 if precision == "fp64" else 1e-5
     for k, v in errs.items():
         assert v < tol, (k, v, errs)
+
+
+@pytest.mark.parametrize("name", ["swap_sphere_n16_T100", "box_n37_T53_ragged"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_single_step_parity_shifted_projection(name, precision):
+    say("single step shifted", name, precision)
+    errs = _single_step(name, precision, shifted=True)
+    say("  errors", {k: "%.2e" % v for k, v in errs.items()})
+    tol = 1e-8 if precision == "fp64" else 1e-5
+    for k, v in errs.items():
+        assert v < tol, (k, v, errs)
+
+
+def test_full_run_shifted_projection_fp64():
+    c = CASES["swap_circle_n4_T50"]
+    say("full run shifted fp64")
+    s, g = c["gen"]()
+    op = _oracle_plan(c)
+    st = am.solve(op, s, g, 100, shifted=True)
+    bt = mato.Batch([_gpu_plan(c, "fp64")], [s], [g])
+    bt.set_projection(True)
+    bt.run(100, 0.0, 25)
+    r_max, _, cost = bt.residuals(0)
+    assert rel(r_max, st.history["r_max"]) < 1e-8
+    assert rel(bt.coeffs(0), st.c) < 1e-9
 
 
 def test_full_run_fp64_swap_circle():

@@ -134,3 +134,29 @@ def test_unclipped_multiplier_orthogonality():
     assert free.sum() > 100 and (~free).sum() > 100
     np.testing.assert_allclose(dot[free], 0.0, atol=1e-12)
     assert np.all(d >= 1.0)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_shifted_projection_is_exact_for_spheres(seed):
+    """Projecting delta + lambda/rho: for spheres the closed form is the exact minimiser
+    of the step-(step_alpha) objective at any multipliers (2-D grid search)."""
+    rng = _rng(500 + seed)
+    r0 = rng.uniform(0.3, 1.5)
+    plan = _plan(r0, r0, rng.uniform(0.5, 2.0))
+    delta = rng.standard_normal(3)
+    lam = rng.standard_normal(3) * 0.7
+    d = rng.uniform(1.0, 3.0)
+    al, be = am.step_alpha_beta(plan, delta[None, None, :], lam[None, None, :], shifted=True)
+    e_cf = am.spheroid_direction(plan, al, be)[0, 0]
+    e_grid, _ = _angle_grid_argmin(plan, delta, d, lam)
+    assert np.max(np.abs(e_cf - e_grid)) < 3 * np.pi / 720 * r0
+
+
+def test_shifted_projection_reduces_to_plain_at_zero_multipliers():
+    plan = _plan(0.3, 0.6)
+    delta = _rng(8).standard_normal((50, 4, 3))
+    lam = np.zeros_like(delta)
+    a1, b1 = am.step_alpha_beta(plan, delta)
+    a2, b2 = am.step_alpha_beta(plan, delta, lam, shifted=True)
+    np.testing.assert_array_equal(a1, a2)
+    np.testing.assert_array_equal(b1, b2)
