@@ -49,6 +49,7 @@ typedef int32_t mato_status;
 
 #define MATO_MAX_AGENTS 160          /* largest n: the pairwise stage keeps one instant of all
                                         n(n-1)/2 pairs in LDS                                  */
+#define MATO_MAX_STAGES 16           /* largest number of stages of a rho schedule             */
 
 /* Trajectory basis of eq. (param): Bernstein polynomials of degree n_coef-1 over
  * [0, t_final] seconds, sampled at T uniformly spaced instants including both ends. */
@@ -94,6 +95,14 @@ mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis,
                              double a, double b, double rho, int32_t precision,
                              void* hip_stream, mato_plan* out);
 void        mato_plan_destroy(mato_plan plan);
+
+/* `count` plans with the same n, T, basis, a, b and precision and the penalties
+ * rhos[0..count) (a rho schedule, Sec. IV-A); their KKT matrices are inverted in the
+ * same launches.  out[m] receives the plan for rhos[m].  Errors as mato_plan_create;
+ * on error no plan is returned. */
+mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                  const double* rhos, int32_t count, int32_t precision,
+                                  void* hip_stream, mato_plan* out);
 
 /* Sizes and diagnostics: n, T, n_coef, precision; cond = ||K||_1 ||K^{-1}||_1 (FP64). */
 mato_status mato_plan_info(mato_plan plan, int32_t* n, int32_t* T, int32_t* n_coef,
@@ -160,6 +169,16 @@ mato_status mato_batch_set_state(mato_batch batch, int32_t q, const void* c,
 /* Linear term g = rho A_fc^T b_fc currently held for problem q, [n][3][n_coef]. */
 mato_status mato_batch_linear_term(mato_batch batch, int32_t q, void* g);
 
+/* Penalty schedule (Sec. IV-A: inverses cached for several increasing rho, the
+ * larger ones used in later iterations).  plans[j * count + q] is problem q's plan in
+ * stage j (same n, T and basis as its creation plan; plans[q] must be the creation
+ * plan itself); stage j starts after start_iter[j] iterations (start_iter[0] = 0,
+ * increasing).  Iteration k of stage j uses rho_j throughout (x-step, d step,
+ * multiplier update).  Call before the first iteration; the caller keeps the plans
+ * alive while the batch exists.  Errors: INVALID_ARG. */
+mato_status mato_batch_set_rho_schedule(mato_batch batch, int32_t stages, const mato_plan* plans,
+                                        const int32_t* start_iter);
+
 /* Projection of the alpha/beta step for every problem of the batch: 0 projects the
  * pairwise difference delta onto the spheroid, eq. (sphere_project) (default); 1 projects
  * delta + lambda/rho, the point the objective of eq. (step_alpha) measures against
@@ -200,6 +219,10 @@ typedef struct {
     int32_t    max_iters;          /* iteration cap per problem, >= 1                      */
     double     tol;                /* convergence threshold on max ||f_c|| (metres)        */
     int32_t    projection;         /* 0: project delta (eq. (sphere_project)); 1: delta + lambda/rho */
+    int32_t    rho_stages;         /* 0: fixed rho; else stages of a rho schedule (<= MATO_MAX_STAGES) */
+    double     rho_values[MATO_MAX_STAGES];  /* rho of each stage (replaces rho)          */
+    int32_t    rho_start[MATO_MAX_STAGES];   /* first iteration of each stage: 0, then
+                                                increasing multiples of chunk            */
 } mato_server_config;
 
 /* Errors: INVALID_ARG (configuration out of range), OUT_OF_MEMORY, HIP. */

@@ -262,3 +262,24 @@ def solve(plan, starts, goals, iters, tol=0.0, shifted=False):
         if st.history["r_max"][-1] < tol:
             break
     return st
+
+
+def solve_schedule(plans, start_iters, starts, goals, iters, tol=0.0, shifted=False):
+    """Algorithm 1 with the penalty parameter increased in stages (Sec. IV-A: inverses
+    cached for several increasing rho, the larger ones used in later iterations).
+
+    plans[j] (same n, T, basis; its own rho and K^{-1}) is used from iteration
+    start_iters[j] on (start_iters[0] = 0, increasing).  Iteration k of stage j uses
+    rho_j throughout: b_fc = d e - lambda/rho_j in the x-step, lambda/rho_j in the d
+    step, lambda += rho_j f_c.
+    """
+    assert start_iters[0] == 0 and all(b > a for a, b in zip(start_iters[:-1], start_iters[1:]))
+    st = initial_state(plans[0], starts, goals)
+    j = 0
+    for k in range(iters):
+        while j + 1 < len(plans) and k >= start_iters[j + 1]:
+            j += 1
+        st = iterate(plans[j], st, shifted)
+        if st.history["r_max"][-1] < tol:
+            break
+    return st

@@ -320,6 +320,45 @@ extern "C" mato_status mato_batch_linear_term(mato_batch b, int32_t q, void* g) 
     });
 }
 
+extern "C" mato_status mato_batch_set_rho_schedule(mato_batch b, int32_t stages, const mato_plan* plans,
+                                                   const int32_t* start_iter) {
+    if (stages < 1 || stages > kMaxStages || !plans || !start_iter || start_iter[0] != 0) {
+        set_error("a schedule needs 1..%d stages, plans and start_iter[0] = 0", kMaxStages);
+        return MATO_ERR_INVALID_ARG;
+    }
+    for (int j = 1; j < stages; ++j)
+        if (start_iter[j] <= start_iter[j - 1]) { set_error("start_iter must increase"); return MATO_ERR_INVALID_ARG; }
+    return dispatch(b, [&](auto* B) -> mato_status {
+        const int cnt = B->count();
+        for (int q = 0; q < cnt; ++q) {
+            const auto& P = B->probs[q];
+            if (P.iters_host != 0) { set_error("set the schedule before the first iteration"); return MATO_ERR_INVALID_ARG; }
+            if (plans[q] != P.plan) { set_error("stage 0 of problem %d must be its creation plan", q); return MATO_ERR_INVALID_ARG; }
+            for (int j = 0; j < stages; ++j) {
+                const mato_plan p = plans[(size_t)j * cnt + q];
+                if (!p || p->n != P.plan->n || p->T != P.plan->T || p->nv != P.plan->nv ||
+                    p->t_final != P.plan->t_final || p->precision != P.plan->precision || p->a != P.plan->a ||
+                    p->b != P.plan->b) {
+                    set_error("stage %d plan of problem %d does not match its sizes, basis or precision", j, q);
+                    return MATO_ERR_INVALID_ARG;
+                }
+            }
+        }
+        MATO_HIP(hipStreamSynchronize(B->stream));
+        for (int q = 0; q < cnt; ++q) {
+            auto& P = B->probs[q];
+            P.stages.clear();
+            P.stage_start.clear();
+            for (int j = 0; j < stages; ++j) {
+                P.stages.push_back(plans[(size_t)j * cnt + q]);
+                P.stage_start.push_back(start_iter[j]);
+            }
+            P.stage = 0;
+        }
+        return B->upload_desc();
+    });
+}
+
 extern "C" mato_status mato_batch_set_projection(mato_batch b, int32_t mode) {
     if (mode != 0 && mode != 1) { set_error("projection mode must be 0 or 1"); return MATO_ERR_INVALID_ARG; }
     return dispatch(b, [&](auto* B) -> mato_status {

@@ -19,6 +19,7 @@ constexpr int kNb = 6;          // boundary rows per agent and axis: p, v, a at 
 constexpr int kMaxCoef = 16;
 constexpr int kHistCap = 4096;  // per-problem iteration history kept on the device
 constexpr int kMaxRefine = 4;
+constexpr int kMaxStages = MATO_MAX_STAGES;
 constexpr int kCtrl = 8;        // control words per problem:
                                 // [0] iterations, [1] stopped, [2] non-finite, [3] active, [4] converged
 
@@ -87,6 +88,9 @@ struct ProblemDesc {
     double tol;                 // convergence threshold on r_max (<= 0: none)
     int iter_cap;               // stop after this many iterations (<= 0: none)
     int shifted;                // 1: project delta + lambda/rho instead of delta
+    int switch_at;              // > 0: iteration count at which the next rho stage starts
+    double rho_next;            // rho of that stage (b_fc and g of the last iteration before it)
+    S sirho_next;               // 1 / rho_next in S
     // optional parity outputs (nullptr = off)
     S* dbg_proj;                // [T][3][np] d e
     S* dbg_d;                   // [T][np]

@@ -85,6 +85,10 @@ struct Engine {
         int nslab = 0;
         int iter_cap = 0;
         int shifted = 0;
+        std::vector<mato_plan> stages;       // rho schedule (empty: the plan throughout)
+        std::vector<int> stage_start;        // first iteration of each stage
+        int stage = 0;
+        int iters_host = 0;                  // iterations enqueued since attach
         std::vector<double> starts, goals;   // [n][3]
     };
 
@@ -260,6 +264,14 @@ struct Engine {
         D.tol = tol;
         D.iter_cap = P.iter_cap;
         D.shifted = P.shifted;
+        D.rho_next = pl->rho;
+        D.sirho_next = (S)(1.0 / pl->rho);
+        D.switch_at = 0;
+        if (P.stage + 1 < (int)P.stages.size()) {
+            D.switch_at = P.stage_start[P.stage + 1];
+            D.rho_next = P.stages[P.stage + 1]->rho;
+            D.sirho_next = (S)(1.0 / P.stages[P.stage + 1]->rho);
+        }
         if (debug && dbg) {
             size_t off = 0;
             for (int k = 0; k < q; ++k) off += (size_t)probs[k].T * 4 * probs[k].np;
@@ -405,6 +417,8 @@ struct Engine {
         }
         P.starts.assign(starts, starts + 3 * (size_t)P.n);
         P.goals.assign(goals, goals + 3 * (size_t)P.n);
+        P.stage = 0;
+        P.iters_host = 0;
         for (size_t k = 0; k < P.starts.size(); ++k)
             if (!std::isfinite(P.starts[k]) || !std::isfinite(P.goals[k])) {
                 set_error("non-finite start or goal");
@@ -573,6 +587,56 @@ struct Engine {
         return MATO_OK;
     }
 
+    mato_status run_segment(int k, bool use_graph, bool per_kernel_events) {
+        if (lists_dirty) MATO_TRY(rebuild_lists());
+        if (active_count() == 0 || k <= 0) return MATO_OK;
+        if (use_graph) {
+            if (!gC && k >= kChunk) MATO_TRY(capture(kChunk, &gC));
+            if (!g1) MATO_TRY(capture(1, &g1));
+            int left = k;
+            while (left >= kChunk) {
+                MATO_HIP(hipGraphLaunch(gC, stream));
+                left -= kChunk;
+            }
+            while (left-- > 0) MATO_HIP(hipGraphLaunch(g1, stream));
+        } else {
+            for (int i = 0; i < k; ++i) MATO_HIP(enqueue_iteration(stream, per_kernel_events));
+        }
+        for (auto& P : probs)
+            if (P.active) P.iters_host += k;
+        return MATO_OK;
+    }
+
+    // Slots whose enqueued iteration count reached their next stage move to it: the
+    // stage's plan (K^{-1}, rho) and its c_eq = K12^{-1} b_eq.
+    mato_status advance_stages() {
+        std::vector<int> moved;
+        for (int q = 0; q < count(); ++q) {
+            Prob& P = probs[q];
+            if (!P.active || P.stage + 1 >= (int)P.stages.size()) continue;
+            if (P.iters_host != P.stage_start[P.stage + 1]) continue;
+            P.stage += 1;
+            P.plan = P.stages[P.stage];
+            double* ki = P.plan->dKinv;
+            MATO_HIP(hipMemcpyAsync(dkinv + q, &ki, sizeof(double*), hipMemcpyHostToDevice, stream));
+            moved.push_back(q);
+        }
+        if (moved.empty()) return MATO_OK;
+        MATO_HIP(hipStreamSynchronize(stream));
+        MATO_TRY(rebuild_lists());
+        for (int q : moved) MATO_HIP(launch_ceq<S>(ddesc + q, dkinv + q, 1, stream));
+        return MATO_OK;
+    }
+
+    // iterations until some active slot reaches its next stage (large if none)
+    int until_next_stage() const {
+        int m = 1 << 30;
+        for (const auto& P : probs)
+            if (P.active && P.stage + 1 < (int)P.stages.size())
+                m = std::min(m, std::max(1, P.stage_start[P.stage + 1] - P.iters_host));
+        return m;
+    }
+
     mato_status step(int k, double new_tol, bool use_graph) {
         if (k < 0) { set_error("negative iteration count"); return MATO_ERR_INVALID_ARG; }
         MATO_TRY(set_tol(new_tol));
@@ -581,19 +645,12 @@ struct Engine {
         last_timed = timing;
         const bool per_kernel_events = timing && !use_graph;
         if (timing) MATO_HIP(hipEventRecord(ev0, stream));
-        if (active_count() > 0) {
-            if (use_graph && k > 0) {
-                if (!gC && k >= kChunk) MATO_TRY(capture(kChunk, &gC));
-                if (!g1) MATO_TRY(capture(1, &g1));
-                int left = k;
-                while (left >= kChunk) {
-                    MATO_HIP(hipGraphLaunch(gC, stream));
-                    left -= kChunk;
-                }
-                while (left-- > 0) MATO_HIP(hipGraphLaunch(g1, stream));
-            } else {
-                for (int i = 0; i < k; ++i) MATO_HIP(enqueue_iteration(stream, per_kernel_events));
-            }
+        int left = k;
+        while (left > 0) {
+            const int seg = std::min(left, until_next_stage());
+            MATO_TRY(run_segment(seg, use_graph, per_kernel_events));
+            MATO_TRY(advance_stages());
+            left -= seg;
         }
         if (timing) MATO_HIP(hipEventRecord(ev1, stream));
         return MATO_OK;

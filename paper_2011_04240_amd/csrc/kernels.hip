@@ -113,6 +113,8 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     gptr<double> part = glob(Dp->part);
     const S ia2 = Dp->ia2, ib2 = Dp->ib2, rho = Dp->srho, irho = Dp->sirho, lzl = Dp->lz;
     const bool shifted = Dp->shifted != 0;
+    // b_fc feeds the next x-step, which uses the next stage's rho on a stage's last iteration
+    const S irho_b = (MODE == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->sirho_next : irho;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S* Xs = reinterpret_cast<S*>(smem_raw);
@@ -245,9 +247,9 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             __builtin_nontemporal_store(nlx, &lam[tb + p]);
             __builtin_nontemporal_store(nly, &lam[tb + np + p]);
             __builtin_nontemporal_store(nlz, &lam[tb + 2 * (size_t)np + p]);
-            Bt[p] = px - nlx * irho;
-            Bt[np + p] = py - nly * irho;
-            Bt[2 * np + p] = pz - nlz * irho;
+            Bt[p] = px - nlx * irho_b;
+            Bt[np + p] = py - nly * irho_b;
+            Bt[2 * np + p] = pz - nlz * irho_b;
             if (dbg_proj_p) {
                 gptr<S> dp = glob(dbg_proj_p);
                 dp[tb + p] = px;
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
     if (!ctrl[3]) return;
     if (mode == kModeIter && ctrl[1]) return;
     const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldq = Dp->ldq;
-    const double rho = Dp->rho;
+    // the linear term of the next x-step: the next stage's rho on a stage's last iteration
+    const double rho = (mode == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->rho_next : Dp->rho;
     gptr<const double> Pm = glob(Dp->P);
     gptr<const S> ss = glob((const S*)Dp->ssum);
     gptr<double> q = glob(Dp->q);

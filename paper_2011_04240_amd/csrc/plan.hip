@@ -98,22 +98,27 @@ __global__ void assemble_kkt(double* __restrict__ W, int n, int nv, int nb, doub
     }
 }
 
-// Column absolute sums of the left half (for ||K||_1) or of the right half.
-__global__ void column_abs_sums(const double* __restrict__ W, int N, int off, double* __restrict__ out) {
+// Column absolute sums of the left half (for ||K||_1) or of the right half; matrix
+// blockIdx.y of a stack with stride ms.
+__global__ void column_abs_sums(const double* __restrict__ W, int N, int off, size_t ms, double* __restrict__ out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
+    const double* Wm = W + ms * blockIdx.y;
     double s = 0.0;
-    for (int r = 0; r < N; ++r) s += fabs(W[(size_t)r * 2 * N + off + c]);
-    out[c] = s;
+    for (int r = 0; r < N; ++r) s += fabs(Wm[(size_t)r * 2 * N + off + c]);
+    out[(size_t)blockIdx.y * N + c] = s;
 }
 
-// Gauss-Jordan step k, part 1 (one workgroup): pivot search over rows >= k (largest
-// |W[r][k]|, lowest r on ties), row swap, pivot-row scaling, and a copy of column k
-// (the elimination factors) into f.
-__global__ __launch_bounds__(1024) void gj_pivot(double* __restrict__ W, int N, int k,
-                                                 double* __restrict__ f, int* __restrict__ flag) {
+// Gauss-Jordan step k, part 1 (one workgroup per matrix of a stack with stride ms):
+// pivot search over rows >= k (largest |W[r][k]|, lowest r on ties), row swap,
+// pivot-row scaling, and a copy of column k (the elimination factors) into f.
+__global__ __launch_bounds__(1024) void gj_pivot(double* __restrict__ Wst, int N, int k, size_t ms,
+                                                 double* __restrict__ fst, int* __restrict__ flags) {
     __shared__ double sv[1024];
     __shared__ int si[1024];
+    __shared__ double s_pv;
+    double* W = Wst + ms * blockIdx.x;
+    double* f = fst + (size_t)N * blockIdx.x;
     const int tid = threadIdx.x;
     const size_t ld = 2 * (size_t)N;
     double best = -1.0;
@@ -133,11 +138,10 @@ __global__ __launch_bounds__(1024) void gj_pivot(double* __restrict__ W, int N, 
         }
         __syncthreads();
     }
-    __shared__ double s_pv;
     const int p = si[0];
     if (tid == 0) {
         s_pv = (p < N) ? W[p * ld + k] : 0.0;
-        if (!(fabs(s_pv) > 1e-300)) flag[0] = 1;
+        if (!(fabs(s_pv) > 1e-300)) flags[blockIdx.x] = 1;
     }
     __syncthreads();                       // the pivot value is read before any row moves
     const double pv = s_pv;
@@ -155,8 +159,11 @@ __global__ __launch_bounds__(1024) void gj_pivot(double* __restrict__ W, int N, 
     for (int r = tid; r < N; r += blockDim.x) f[r] = (r == k) ? 0.0 : W[(size_t)r * ld + k];
 }
 
-// Gauss-Jordan step k, part 2: W[r][c] -= f[r] W[k][c] for every r != k and c >= k.
-__global__ void gj_eliminate(double* __restrict__ W, int N, int k, const double* __restrict__ f) {
+// Gauss-Jordan step k, part 2: W[r][c] -= f[r] W[k][c] for every r != k and c >= k,
+// matrix blockIdx.y of the stack.
+__global__ void gj_eliminate(double* __restrict__ Wst, int N, int k, size_t ms, const double* __restrict__ fst) {
+    double* W = Wst + ms * blockIdx.y;
+    const double* f = fst + (size_t)N * blockIdx.y;
     const size_t ld = 2 * (size_t)N;
     const int ncols = 2 * N - k;
     const size_t total = (size_t)N * ncols;
@@ -216,44 +223,50 @@ static int grid_for(size_t total, int block) {
     return (int)g;
 }
 
-// Inverts the N x N matrix assembled into W (left half) in place; result in `inv`.
-// Returns SINGULAR on a zero pivot; writes ||K||_1 ||K^{-1}||_1 to *cond.
-static mato_status gauss_jordan(double* W, int N, double* inv, double* cond, hipStream_t st) {
+// Inverts `count` N x N matrices assembled into the left halves of a stack of
+// augmented matrices W (stride N x 2N), all in the same launches; inverse m goes to
+// inv[m].  Returns SINGULAR on a zero pivot; writes ||K||_1 ||K^{-1}||_1 to cond[m].
+static mato_status gauss_jordan(double* W, int N, int count, double* const* inv, double* cond, hipStream_t st) {
+    const size_t ms = (size_t)N * 2 * N;
     double *f = nullptr, *cs = nullptr;
     int* flag = nullptr;
-    MATO_HIP(hipMalloc(&f, sizeof(double) * N));
-    MATO_HIP(hipMalloc(&cs, sizeof(double) * N));
-    MATO_HIP(hipMalloc(&flag, sizeof(int)));
-    MATO_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-    std::vector<double> h(N);
-    column_abs_sums<<<(N + 255) / 256, 256, 0, st>>>(W, N, 0, cs);
-    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    MATO_HIP(hipMalloc(&f, sizeof(double) * N * count));
+    MATO_HIP(hipMalloc(&cs, sizeof(double) * N * count));
+    MATO_HIP(hipMalloc(&flag, sizeof(int) * count));
+    MATO_HIP(hipMemsetAsync(flag, 0, sizeof(int) * count, st));
+    std::vector<double> h((size_t)N * count), norm1(count, 0.0);
+    column_abs_sums<<<dim3((N + 255) / 256, count), 256, 0, st>>>(W, N, 0, ms, cs);
+    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
     MATO_HIP(hipStreamSynchronize(st));
-    double norm1 = 0.0;
-    for (double v : h) norm1 = std::max(norm1, v);
+    for (int m = 0; m < count; ++m)
+        for (int c = 0; c < N; ++c) norm1[m] = std::max(norm1[m], h[(size_t)m * N + c]);
     for (int k = 0; k < N; ++k) {
-        gj_pivot<<<1, 1024, 0, st>>>(W, N, k, f, flag);
+        gj_pivot<<<count, 1024, 0, st>>>(W, N, k, ms, f, flag);
         const size_t work = (size_t)N * (2 * N - k);
-        gj_eliminate<<<grid_for(work, 256), 256, 0, st>>>(W, N, k, f);
+        gj_eliminate<<<dim3(grid_for(work, 256), count), 256, 0, st>>>(W, N, k, ms, f);
     }
     MATO_HIP(hipGetLastError());
-    column_abs_sums<<<(N + 255) / 256, 256, 0, st>>>(W, N, N, cs);
-    int hflag = 0;
-    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    MATO_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    extract_inverse<<<grid_for((size_t)N * N, 256), 256, 0, st>>>(W, N, inv);
+    column_abs_sums<<<dim3((N + 255) / 256, count), 256, 0, st>>>(W, N, N, ms, cs);
+    std::vector<int> hflag(count, 0);
+    MATO_HIP(hipMemcpyAsync(h.data(), cs, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    MATO_HIP(hipMemcpyAsync(hflag.data(), flag, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    for (int m = 0; m < count; ++m)
+        extract_inverse<<<grid_for((size_t)N * N, 256), 256, 0, st>>>(W + ms * m, N, inv[m]);
     MATO_HIP(hipStreamSynchronize(st));
     dfree(f);
     dfree(cs);
     dfree(flag);
-    double ninv = 0.0;
-    for (double v : h) ninv = std::max(ninv, v);
-    *cond = norm1 * ninv;
-    if (hflag || !std::isfinite(*cond) || *cond > 1e14) {
-        set_error("KKT matrix is singular or too ill-conditioned (cond estimate %.3e)", *cond);
-        return MATO_ERR_SINGULAR;
+    mato_status status = MATO_OK;
+    for (int m = 0; m < count; ++m) {
+        double ninv = 0.0;
+        for (int c = 0; c < N; ++c) ninv = std::max(ninv, h[(size_t)m * N + c]);
+        cond[m] = norm1[m] * ninv;
+        if (hflag[m] || !std::isfinite(cond[m]) || cond[m] > 1e14) {
+            set_error("KKT matrix is singular or too ill-conditioned (cond estimate %.3e)", cond[m]);
+            status = MATO_ERR_SINGULAR;
+        }
     }
-    return MATO_OK;
+    return status;
 }
 
 template <typename T>
@@ -264,30 +277,37 @@ static mato_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
     return MATO_OK;
 }
 
-static mato_status plan_build(mato_plan p) {
-    const int n = p->n, nv = p->nv, nb = p->nb, T = p->T;
-    hipStream_t st = p->stream;
-    bernstein_basis(nv, T, p->t_final, p->P, p->Pd, p->Pdd);
-    gram(p->P, T, nv, p->PtP);
-    gram(p->Pdd, T, nv, p->PddtPdd);
-    p->A.assign((size_t)nb * nv, 0.0);
+// Builds plans that share n, T, basis, a, b and precision and differ in rho; their
+// KKT matrices are inverted together.
+static mato_status plans_build(std::vector<mato_plan>& ps) {
+    mato_plan p0 = ps[0];
+    const int n = p0->n, nv = p0->nv, nb = p0->nb, T = p0->T, cnt = (int)ps.size();
+    hipStream_t st = p0->stream;
+    bernstein_basis(nv, T, p0->t_final, p0->P, p0->Pd, p0->Pdd);
+    gram(p0->P, T, nv, p0->PtP);
+    gram(p0->Pdd, T, nv, p0->PddtPdd);
+    p0->A.assign((size_t)nb * nv, 0.0);
     for (int j = 0; j < nv; ++j) {
-        p->A[0 * nv + j] = p->P[j];
-        p->A[1 * nv + j] = p->Pd[j];
-        p->A[2 * nv + j] = p->Pdd[j];
-        p->A[3 * nv + j] = p->P[(size_t)(T - 1) * nv + j];
-        p->A[4 * nv + j] = p->Pd[(size_t)(T - 1) * nv + j];
-        p->A[5 * nv + j] = p->Pdd[(size_t)(T - 1) * nv + j];
+        p0->A[0 * nv + j] = p0->P[j];
+        p0->A[1 * nv + j] = p0->Pd[j];
+        p0->A[2 * nv + j] = p0->Pdd[j];
+        p0->A[3 * nv + j] = p0->P[(size_t)(T - 1) * nv + j];
+        p0->A[4 * nv + j] = p0->Pd[(size_t)(T - 1) * nv + j];
+        p0->A[5 * nv + j] = p0->Pdd[(size_t)(T - 1) * nv + j];
     }
-    MATO_TRY(upload(&p->dP, p->P, &p->bytes));
-    MATO_TRY(upload(&p->dPdd, p->Pdd, &p->bytes));
-    MATO_TRY(upload(&p->dPtP, p->PtP, &p->bytes));
-    MATO_TRY(upload(&p->dPddtPdd, p->PddtPdd, &p->bytes));
-    MATO_TRY(upload(&p->dA, p->A, &p->bytes));
-    {
-        std::vector<unsigned> pairs;
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j) pairs.push_back((unsigned)i | ((unsigned)j << 16));
+    std::vector<unsigned> pairs;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) pairs.push_back((unsigned)i | ((unsigned)j << 16));
+    for (auto p : ps) {
+        if (p != p0) {
+            p->P = p0->P; p->Pd = p0->Pd; p->Pdd = p0->Pdd;
+            p->PtP = p0->PtP; p->PddtPdd = p0->PddtPdd; p->A = p0->A;
+        }
+        MATO_TRY(upload(&p->dP, p->P, &p->bytes));
+        MATO_TRY(upload(&p->dPdd, p->Pdd, &p->bytes));
+        MATO_TRY(upload(&p->dPtP, p->PtP, &p->bytes));
+        MATO_TRY(upload(&p->dPddtPdd, p->PddtPdd, &p->bytes));
+        MATO_TRY(upload(&p->dA, p->A, &p->bytes));
         MATO_TRY(upload(&p->dPairs, pairs, &p->bytes));
     }
 
@@ -302,51 +322,68 @@ static mato_status plan_build(mato_plan p) {
         MATO_HIP(hipMemcpy(dzero, zeros.data(), sizeof(double) * nv * nv, hipMemcpyHostToDevice));
         // n = 1, rho = 0: H = Pdd^T Pdd
         assemble_kkt<<<grid_for((size_t)N0 * 2 * N0, 256), 256, 0, st>>>(W0, 1, nv, nb, 0.0, dzero,
-                                                                         p->dPddtPdd, p->dA);
+                                                                         p0->dPddtPdd, p0->dA);
         double c0 = 0.0;
-        mato_status s = gauss_jordan(W0, N0, inv0, &c0, st);
+        mato_status s = gauss_jordan(W0, N0, 1, &inv0, &c0, st);
         if (s == MATO_OK) {
             std::vector<double> h((size_t)N0 * N0);
             MATO_HIP(hipMemcpy(h.data(), inv0, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
-            p->K0inv_c.assign((size_t)nv * nb, 0.0);
+            p0->K0inv_c.assign((size_t)nv * nb, 0.0);
             for (int r = 0; r < nv; ++r)
-                for (int b = 0; b < nb; ++b) p->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
+                for (int b = 0; b < nb; ++b) p0->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
         }
         dfree(W0);
         dfree(inv0);
         dfree(dzero);
         if (s != MATO_OK) return s;
-        MATO_TRY(upload(&p->dK0c, p->K0inv_c, &p->bytes));
+        for (auto p : ps) {
+            if (p != p0) p->K0inv_c = p0->K0inv_c;
+            MATO_TRY(upload(&p->dK0c, p->K0inv_c, &p->bytes));
+        }
     }
 
-    // full KKT matrix of eq. (kkt_step_x) and its inverse
+    // KKT matrices of eq. (kkt_step_x), one per rho, inverted together
     const int N = n * (nv + nb), M = n * nv;
+    const size_t ms = (size_t)N * 2 * N;
     double* W = nullptr;
-    MATO_HIP(hipMalloc(&W, sizeof(double) * (size_t)N * 2 * N));
-    MATO_HIP(hipMalloc(&p->dKinv, sizeof(double) * (size_t)N * N));
-    p->bytes += sizeof(double) * (size_t)N * N;
-    assemble_kkt<<<grid_for((size_t)N * 2 * N, 256), 256, 0, st>>>(W, n, nv, nb, p->rho, p->dPtP,
-                                                                   p->dPddtPdd, p->dA);
-    mato_status s = gauss_jordan(W, N, p->dKinv, &p->cond, st);
+    if (hipMalloc(&W, sizeof(double) * ms * cnt) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed", sizeof(double) * ms * cnt);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
+    std::vector<double*> invs(cnt);
+    std::vector<double> conds(cnt, 0.0);
+    for (int m = 0; m < cnt; ++m) {
+        MATO_HIP(hipMalloc(&ps[m]->dKinv, sizeof(double) * (size_t)N * N));
+        ps[m]->bytes += sizeof(double) * (size_t)N * N;
+        invs[m] = ps[m]->dKinv;
+        assemble_kkt<<<grid_for(ms, 256), 256, 0, st>>>(W + ms * m, n, nv, nb, ps[m]->rho, ps[m]->dPtP,
+                                                        ps[m]->dPddtPdd, ps[m]->dA);
+    }
+    mato_status s = gauss_jordan(W, N, cnt, invs.data(), conds.data(), st);
     dfree(W);
+    for (int m = 0; m < cnt; ++m) ps[m]->cond = conds[m];
     if (s != MATO_OK) return s;
 
     // GEMM operand: the (11n x 11n) block K11^{-1}; the K12^{-1} b_eq part is formed once
     // per problem in FP64
     const int Mp = round_up(M, 64);
-    p->ldk = round_up(M, 32);
-    const size_t elems = (size_t)Mp * p->ldk;
+    const int ldk = round_up(M, 32);
+    const size_t elems = (size_t)Mp * ldk;
     int kind = 0;
     size_t esz = sizeof(float);
-    if (p->precision == MATO_BF16_REFINED) { kind = 1; esz = 2; }
-    if (p->precision == MATO_FP64) { kind = 2; esz = sizeof(double); }
-    MATO_HIP(hipMalloc(&p->dAhi, esz * elems));
-    p->bytes += esz * elems;
-    if (kind == 1) {
-        MATO_HIP(hipMalloc(&p->dAlo, esz * elems));
+    if (p0->precision == MATO_BF16_REFINED) { kind = 1; esz = 2; }
+    if (p0->precision == MATO_FP64) { kind = 2; esz = sizeof(double); }
+    for (auto p : ps) {
+        p->ldk = ldk;
+        MATO_HIP(hipMalloc(&p->dAhi, esz * elems));
         p->bytes += esz * elems;
+        if (kind == 1) {
+            MATO_HIP(hipMalloc(&p->dAlo, esz * elems));
+            p->bytes += esz * elems;
+        }
+        extract_crows<<<grid_for(elems, 256), 256, 0, st>>>(p->dKinv, N, M, Mp, ldk, kind, p->dAhi, p->dAlo);
     }
-    extract_crows<<<grid_for(elems, 256), 256, 0, st>>>(p->dKinv, N, M, Mp, p->ldk, kind, p->dAhi, p->dAlo);
     MATO_HIP(hipGetLastError());
     MATO_HIP(hipStreamSynchronize(st));
     return MATO_OK;
@@ -374,41 +411,65 @@ extern "C" void mato_plan_destroy(mato_plan p) {
     delete p;
 }
 
-extern "C" mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis, double a,
-                                        double b, double rho, int32_t precision, void* hip_stream,
-                                        mato_plan* out) {
-    if (!out || !basis) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
-    *out = nullptr;
+static mato_status check_plan_args(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                   int32_t precision) {
+    if (!basis) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
     if (basis->kind != MATO_BASIS_BERNSTEIN) { set_error("unknown basis kind %d", basis->kind); return MATO_ERR_INVALID_ARG; }
     if (basis->n_coef < 6 || basis->n_coef > kMaxCoef) { set_error("n_coef %d outside 6..%d", basis->n_coef, kMaxCoef); return MATO_ERR_INVALID_ARG; }
     if (n < 2) { set_error("n = %d < 2", n); return MATO_ERR_INVALID_ARG; }
     if (n > MATO_MAX_AGENTS) { set_error("n = %d > %d", n, MATO_MAX_AGENTS); return MATO_ERR_UNSUPPORTED; }
     if (T < basis->n_coef) { set_error("T = %d < n_coef", T); return MATO_ERR_INVALID_ARG; }
-    if (!(a > 0) || !(b > 0) || !(rho > 0) || !(basis->t_final > 0) || !std::isfinite(a) ||
-        !std::isfinite(b) || !std::isfinite(rho) || !std::isfinite(basis->t_final)) {
-        set_error("a, b, rho and t_final must be finite and > 0");
+    if (!(a > 0) || !(b > 0) || !(basis->t_final > 0) || !std::isfinite(a) || !std::isfinite(b) ||
+        !std::isfinite(basis->t_final)) {
+        set_error("a, b and t_final must be finite and > 0");
         return MATO_ERR_INVALID_ARG;
     }
     if (precision != MATO_FP64 && precision != MATO_FP32 && precision != MATO_BF16_REFINED) {
         set_error("unknown precision %d", precision);
         return MATO_ERR_INVALID_ARG;
     }
-    mato_plan p = new mato_plan_s();
-    p->n = n; p->T = T; p->nv = basis->n_coef; p->nb = kNb; p->precision = precision;
-    p->t_final = basis->t_final; p->a = a; p->b = b; p->rho = rho; p->cond = 0.0;
-    p->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&p->device) != hipSuccess) {
+    return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                             const double* rhos, int32_t count, int32_t precision,
+                                             void* hip_stream, mato_plan* out) {
+    if (!out || !rhos || count < 1) { set_error("null argument or count < 1"); return MATO_ERR_INVALID_ARG; }
+    for (int m = 0; m < count; ++m) out[m] = nullptr;
+    MATO_TRY(check_plan_args(n, T, basis, a, b, precision));
+    for (int m = 0; m < count; ++m)
+        if (!(rhos[m] > 0) || !std::isfinite(rhos[m])) { set_error("rho must be finite and > 0"); return MATO_ERR_INVALID_ARG; }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) {
         set_error("no HIP device");
-        delete p;
         return MATO_ERR_HIP;
     }
-    mato_status s = plan_build(p);
+    std::vector<mato_plan> ps;
+    for (int m = 0; m < count; ++m) {
+        mato_plan p = new mato_plan_s();
+        p->n = n; p->T = T; p->nv = basis->n_coef; p->nb = kNb; p->precision = precision;
+        p->t_final = basis->t_final; p->a = a; p->b = b; p->rho = rhos[m]; p->cond = 0.0;
+        p->stream = (hipStream_t)hip_stream;
+        p->device = device;
+        ps.push_back(p);
+    }
+    mato_status s = plans_build(ps);
     if (s != MATO_OK) {
-        mato_plan_destroy(p);
+        for (auto p : ps) mato_plan_destroy(p);
         return s;
     }
-    *out = p;
+    for (int m = 0; m < count; ++m) out[m] = ps[m];
     return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis, double a,
+                                        double b, double rho, int32_t precision, void* hip_stream,
+                                        mato_plan* out) {
+    if (!out || !basis) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    *out = nullptr;
+    MATO_TRY(check_plan_args(n, T, basis, a, b, precision));
+    if (!(rho > 0) || !std::isfinite(rho)) { set_error("a, b, rho and t_final must be finite and > 0"); return MATO_ERR_INVALID_ARG; }
+    return mato_plan_create_many(n, T, basis, a, b, &rho, 1, precision, hip_stream, out);
 }
 
 extern "C" mato_status mato_plan_info(mato_plan p, int32_t* n, int32_t* T, int32_t* n_coef,

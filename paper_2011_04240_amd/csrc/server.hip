@@ -22,7 +22,7 @@ struct mato_server_s {
     mato_server_config cfg;
     hipStream_t stream = nullptr;
     void* eng = nullptr;                       // mato::Engine<float> or <double>
-    std::map<int, mato_plan> plans;            // per agent count
+    std::map<int, mato_plan> plans;            // per (agent count, rho stage): key n * kMaxStages + stage
     struct Req {
         int64_t id = 0;
         int n = 0;
@@ -65,14 +65,18 @@ struct ServerOps {
     }
 
     static bool plan_in_use(mato_server s, mato_plan p) {
-        for (auto& P : E(s)->probs)
-            if (P.active && P.plan == p) return true;
+        for (auto& P : E(s)->probs) {
+            if (!P.active) continue;
+            if (P.plan == p) return true;
+            for (auto q : P.stages)
+                if (q == p) return true;
+        }
         return false;
     }
 
     // Frees idle device memory (blocks of free slots, then unused plans) until `need`
-    // more bytes fit the budget; `keep` is a plan that must stay.
-    static bool make_room(mato_server s, size_t need, mato_plan keep, int keep_slot) {
+    // more bytes fit the budget; the plans in `keep` must stay.
+    static bool make_room(mato_server s, size_t need, const std::vector<mato_plan>& keep, int keep_slot) {
         const double budget = s->cfg.hbm_budget_bytes;
         if (budget <= 0) return true;
         auto fits = [&]() { return (double)(device_bytes(s) + need) <= budget; };
@@ -81,7 +85,7 @@ struct ServerOps {
         for (int q = 0; q < e->count() && !fits(); ++q)
             if (q != keep_slot && !e->probs[q].active && e->probs[q].own) e->release_block(q);
         for (auto it = s->plans.begin(); it != s->plans.end() && !fits();) {
-            if (it->second != keep && !plan_in_use(s, it->second)) {
+            if (!plan_keep(s, it->second, keep) && !plan_in_use(s, it->second)) {
                 for (int q = 0; q < e->count(); ++q)
                     if (!e->probs[q].active && e->probs[q].plan == it->second) e->release_block(q);
                 mato_plan_destroy(it->second);
@@ -93,22 +97,39 @@ struct ServerOps {
         return fits();
     }
 
-    static mato_status get_plan(mato_server s, int n, mato_plan* out) {
-        auto it = s->plans.find(n);
-        if (it != s->plans.end()) {
-            *out = it->second;
-            return MATO_OK;
+    static int stages(mato_server s) { return s->cfg.rho_stages > 0 ? s->cfg.rho_stages : 1; }
+    static double stage_rho(mato_server s, int j) { return s->cfg.rho_stages > 0 ? s->cfg.rho_values[j] : s->cfg.rho; }
+
+    static bool plan_keep(mato_server s, mato_plan p, const std::vector<mato_plan>& keep) {
+        for (auto k : keep)
+            if (k == p) return true;
+        return false;
+    }
+
+    // All stage plans of agent count n (created on demand, together, within the budget).
+    static mato_status get_plans(mato_server s, int n, std::vector<mato_plan>* out) {
+        out->clear();
+        std::vector<int> missing;
+        std::vector<double> rhos;
+        for (int j = 0; j < stages(s); ++j)
+            if (!s->plans.count(n * kMaxStages + j)) {
+                missing.push_back(j);
+                rhos.push_back(stage_rho(s, j));
+            }
+        if (!missing.empty()) {
+            std::vector<mato_plan> keep;
+            for (int j = 0; j < stages(s); ++j) {
+                auto it = s->plans.find(n * kMaxStages + j);
+                if (it != s->plans.end()) keep.push_back(it->second);
+            }
+            const size_t est = missing.size() * plan_bytes_estimate(n, s->cfg.basis.n_coef, s->cfg.T, s->cfg.precision);
+            if (!make_room(s, est, keep, -1)) return MATO_OK;     // not now: wait for memory
+            std::vector<mato_plan> made(missing.size(), nullptr);
+            MATO_TRY(mato_plan_create_many(n, s->cfg.T, &s->cfg.basis, s->cfg.a, s->cfg.b, rhos.data(),
+                                           (int)rhos.size(), s->cfg.precision, s->stream, made.data()));
+            for (size_t m = 0; m < missing.size(); ++m) s->plans[n * kMaxStages + missing[m]] = made[m];
         }
-        const size_t est = plan_bytes_estimate(n, s->cfg.basis.n_coef, s->cfg.T, s->cfg.precision);
-        if (!make_room(s, est, nullptr, -1)) {
-            *out = nullptr;
-            return MATO_OK;                    // not now: wait for memory
-        }
-        mato_plan p = nullptr;
-        MATO_TRY(mato_plan_create(n, s->cfg.T, &s->cfg.basis, s->cfg.a, s->cfg.b, s->cfg.rho, s->cfg.precision,
-                                  s->stream, &p));
-        s->plans[n] = p;
-        *out = p;
+        for (int j = 0; j < stages(s); ++j) out->push_back(s->plans[n * kMaxStages + j]);
         return MATO_OK;
     }
 
@@ -160,9 +181,10 @@ struct ServerOps {
         std::vector<int> admitted;
         while (!s->queue.empty()) {
             auto& R = s->reqs[s->queue.front()];
-            mato_plan plan = nullptr;
-            MATO_TRY(get_plan(s, R.n, &plan));
-            if (!plan) break;
+            std::vector<mato_plan> sp;
+            MATO_TRY(get_plans(s, R.n, &sp));
+            if (sp.empty()) break;
+            const mato_plan plan = sp[0];
             const size_t need = Engine<S>::slot_bytes(plan);
             int q = -1;
             for (int k = 0; k < e->count() && q < 0; ++k)      // a free slot whose block fits
@@ -173,11 +195,18 @@ struct ServerOps {
             const bool reuse = e->probs[q].own && e->probs[q].block >= need;
             if (!reuse) {
                 e->release_block(q);
-                if (!make_room(s, need, plan, q)) break;
+                if (!make_room(s, need, sp, q)) break;
             }
             e->probs[q].iter_cap = s->cfg.max_iters;
             e->probs[q].shifted = s->cfg.projection;
             MATO_TRY(e->attach(q, plan, R.starts.data(), R.goals.data(), nullptr));
+            e->probs[q].stages.clear();
+            e->probs[q].stage_start.clear();
+            if (s->cfg.rho_stages > 0)
+                for (int j = 0; j < stages(s); ++j) {
+                    e->probs[q].stages.push_back(sp[j]);
+                    e->probs[q].stage_start.push_back(s->cfg.rho_start[j]);
+                }
             s->slot_req[q] = R.id;
             R.state = 1;
             R.slot = q;
@@ -236,10 +265,16 @@ extern "C" mato_status mato_server_create(const mato_server_config* cfg, void* h
     if (cfg->max_slots < 1 || cfg->chunk < 1 || cfg->max_iters < 1 || cfg->T < cfg->basis.n_coef ||
         !(cfg->a > 0) || !(cfg->b > 0) || !(cfg->rho > 0) || !(cfg->basis.t_final > 0) ||
         (cfg->precision != MATO_FP64 && cfg->precision != MATO_FP32 && cfg->precision != MATO_BF16_REFINED) ||
-        (cfg->projection != 0 && cfg->projection != 1)) {
+        (cfg->projection != 0 && cfg->projection != 1) || cfg->rho_stages < 0 || cfg->rho_stages > kMaxStages) {
         set_error("invalid server configuration");
         return MATO_ERR_INVALID_ARG;
     }
+    for (int j = 0; j < cfg->rho_stages; ++j)
+        if (!(cfg->rho_values[j] > 0) || cfg->rho_start[j] % cfg->chunk != 0 || (j == 0 && cfg->rho_start[0] != 0) ||
+            (j > 0 && cfg->rho_start[j] <= cfg->rho_start[j - 1])) {
+            set_error("rho schedule: values > 0, starts 0 then increasing multiples of chunk");
+            return MATO_ERR_INVALID_ARG;
+        }
     auto* s = new mato_server_s();
     s->cfg = *cfg;
     s->stream = (hipStream_t)hip_stream;
@@ -265,9 +300,9 @@ extern "C" void mato_server_destroy(mato_server s) {
 extern "C" mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_max) {
     return sdispatch(s, [&](auto ops) -> mato_status {
         for (int n = std::max(2, (int)n_min); n <= n_max; ++n) {
-            mato_plan p = nullptr;
-            MATO_TRY(ops.get_plan(s, n, &p));
-            if (!p) { set_error("device-memory budget too small to hold the plan for n = %d", n); return MATO_ERR_OUT_OF_MEMORY; }
+            std::vector<mato_plan> p;
+            MATO_TRY(ops.get_plans(s, n, &p));
+            if (p.empty()) { set_error("device-memory budget too small to hold the plans for n = %d", n); return MATO_ERR_OUT_OF_MEMORY; }
         }
         return MATO_OK;
     });

@@ -25,6 +25,7 @@ MATO_ERR_UNSUPPORTED = -6
 MATO_ERR_NOT_FOUND = -7
 MATO_WARN_NOT_CONVERGED = 1
 MATO_MAX_AGENTS = 160
+MATO_MAX_STAGES = 16
 
 MATO_FP64, MATO_FP32, MATO_BF16_REFINED = 0, 1, 2
 PRECISIONS = {"fp64": MATO_FP64, "fp32": MATO_FP32, "bf16": MATO_BF16_REFINED}
@@ -44,7 +45,8 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("basis", _Basis), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("rho", ctypes.c_double), ("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_double), ("chunk", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("projection", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("projection", ctypes.c_int32), ("rho_stages", ctypes.c_int32),
+                ("rho_values", ctypes.c_double * 16), ("rho_start", ctypes.c_int32 * 16)]
 
 
 _lib = None
@@ -57,6 +59,7 @@ SIGNATURES = {
     "mato_version": (ctypes.c_char_p, []),
     "mato_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _f64, _i32, _vp, _pvp]),
     "mato_plan_destroy": (None, [_vp]),
+    "mato_plan_create_many": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _pf64, _i32, _i32, _vp, _pvp]),
     "mato_plan_info": (_i32, [_vp, _pi32, _pi32, _pi32, _pi32, _pf64]),
     "mato_plan_inverse": (_i32, [_vp, _vp]),
     "mato_batch_create": (_i32, [_i32, _pvp, _vp, _vp, _vp, _pvp]),
@@ -71,6 +74,7 @@ SIGNATURES = {
     "mato_batch_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mato_batch_set_state": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "mato_batch_linear_term": (_i32, [_vp, _i32, _vp]),
+    "mato_batch_set_rho_schedule": (_i32, [_vp, _i32, _pvp, _pi32]),
     "mato_batch_set_projection": (_i32, [_vp, _i32]),
     "mato_batch_set_tiles": (_i32, [_vp, _i32, _i32]),
     "mato_batch_get_tiles": (_i32, [_vp, _pi32, _pi32]),
@@ -149,6 +153,15 @@ def mato_plan_create(n, T, n_coef, t_final, a, b, rho, precision, stream=None):
     return h
 
 
+def mato_plan_create_many(n, T, n_coef, t_final, a, b, rhos, precision, stream=None):
+    out = (ctypes.c_void_p * len(rhos))()
+    r = (ctypes.c_double * len(rhos))(*rhos)
+    basis = _Basis(0, n_coef, t_final)
+    _check(lib().mato_plan_create_many(n, T, ctypes.byref(basis), a, b, r, len(rhos), precision,
+                                       _stream_ptr(stream), out))
+    return [ctypes.c_void_p(x) for x in out]
+
+
 def mato_plan_destroy(plan):
     lib().mato_plan_destroy(plan)
 
@@ -219,6 +232,13 @@ def mato_batch_set_state(batch, q, c, lam, proj):
 
 def mato_batch_linear_term(batch, q, out):
     _check(lib().mato_batch_linear_term(batch, q, _ptr(out)))
+
+
+def mato_batch_set_rho_schedule(batch, plans, start_iter):
+    """plans: stage-major list of plan handles ([stage][problem]); start_iter per stage."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    st = (ctypes.c_int32 * len(start_iter))(*start_iter)
+    _check(lib().mato_batch_set_rho_schedule(batch, len(start_iter), arr, st))
 
 
 def mato_batch_set_projection(batch, mode):
@@ -305,11 +325,20 @@ def mato_server_run_trace(server, arrival_s, ns, starts, goals, latency, iters, 
 class Plan:
     """K^{-1} of the x/y/z step for one (n, T, basis, rho); a, b are the spheroid dimensions."""
 
-    def __init__(self, n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", stream=None):
+    def __init__(self, n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", stream=None,
+                 handle=None):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.n, self.T, self.n_coef = n, T, n_coef
         self.t_final, self.a, self.b, self.rho = t_final, a, b, rho
-        self.handle = mato_plan_create(n, T, n_coef, t_final, a, b, rho, self.precision, stream)
+        self.handle = handle if handle is not None else mato_plan_create(n, T, n_coef, t_final, a, b, rho,
+                                                                          self.precision, stream)
+
+    @classmethod
+    def schedule(cls, n, T, rhos, n_coef=11, t_final=10.0, a=0.3, b=0.6, precision="fp32", stream=None):
+        """Plans for several rho (a rho schedule), inverted together."""
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        hs = mato_plan_create_many(n, T, n_coef, t_final, a, b, list(rhos), pr, stream)
+        return [cls(n, T, n_coef, t_final, a, b, r, pr, handle=h) for r, h in zip(rhos, hs)]
 
     @property
     def scalar(self):
@@ -340,11 +369,18 @@ class Server:
     """Continuous-batching request loop (problems of any agent count up to MATO_MAX_AGENTS)."""
 
     def __init__(self, T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", max_slots=64,
-                 hbm_budget_bytes=0.0, chunk=10, max_iters=2000, tol=1e-3, shifted=False, stream=None):
+                 hbm_budget_bytes=0.0, chunk=10, max_iters=2000, tol=1e-3, shifted=False, rho_schedule=None,
+                 stream=None):
         self.T, self.n_coef = T, n_coef
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = ServerConfig(T, _Basis(0, n_coef, t_final), a, b, rho, self.precision, max_slots, hbm_budget_bytes,
                            chunk, max_iters, tol, int(bool(shifted)))
+        if rho_schedule is not None:
+            values, starts = rho_schedule
+            cfg.rho_stages = len(values)
+            for j, (v, t) in enumerate(zip(values, starts)):
+                cfg.rho_values[j] = v
+                cfg.rho_start[j] = t
         self.handle = mato_server_create(cfg, stream)
 
     def warm(self, n_min, n_max):
@@ -461,6 +497,12 @@ class Batch:
         out = np.empty((p.n, 3, p.n_coef), np.float64)
         mato_batch_linear_term(self.handle, q, out)
         return out
+
+    def set_rho_schedule(self, stage_plans, start_iter):
+        """stage_plans[j][q]: problem q's plan in stage j (stage 0: the creation plans)."""
+        flat = [p.handle for stage in stage_plans for p in stage]
+        self._stage_plans = stage_plans            # keep them alive with the batch
+        mato_batch_set_rho_schedule(self.handle, flat, list(start_iter))
 
     def set_projection(self, shifted):
         mato_batch_set_projection(self.handle, int(bool(shifted)))
