@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the served-latency sweep over arrival rates 10..500 /s")
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--serve-fixed-rho", action="store_true",
+                    help="serve with one rho instead of the increasing schedule")
     return ap.parse_args()
 
 
@@ -103,9 +105,14 @@ def cpu_baseline(n, T, seconds):
                       % (n, T, iters, dt)}
 
 
-def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_iters=2000, tol=1e-3):
+RHO_SCHEDULE = ([2.0 ** j for j in range(10)], [30 * j for j in range(10)])
+
+
+def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_iters=2000, tol=1e-3,
+                schedule=True):
     """Poisson arrivals of random-box problems (n uniform over 4..128, box at the n=64
-    density) replayed in real time through the server; latency = finish - arrival."""
+    density) replayed in real time through the server; latency = finish - arrival.
+    With `schedule`, ten increasing rho (doubling every 30 iterations, Sec. IV-A)."""
     from paper_2011_04240_amd import mato
     from paper_2011_04240_amd import scenarios as sc
     rng = np.random.Generator(np.random.PCG64(1000 + seed))
@@ -113,7 +120,8 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
     scen = [sc.random_density_box(n, seed=10000 * (seed + 1) + k) for k, n in enumerate(ns)]
     arr = sc.poisson_arrivals(rate, count, seed=seed)
     srv = mato.Server(T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision=precision,
-                      max_slots=max_slots, chunk=chunk, max_iters=max_iters, tol=tol)
+                      max_slots=max_slots, chunk=chunk, max_iters=max_iters, tol=tol,
+                      rho_schedule=RHO_SCHEDULE if schedule else None)
     t0 = time.perf_counter()
     srv.warm(4, 128)
     warm_s = time.perf_counter() - t0
@@ -125,7 +133,8 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
             "throughput_problems_per_s": count / wall, "updates_per_s": upd / wall,
             "converged_frac": float(np.mean(conv)), "capped_frac": float(np.mean(its >= max_iters)),
             "mean_iters": float(np.mean(its)), "wall_s": wall, "plan_warm_s": warm_s,
-            "precision": precision, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol}
+            "precision": precision, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol,
+            "rho": ({"values": RHO_SCHEDULE[0], "start_iter": RHO_SCHEDULE[1]} if schedule else 1.0)}
 
 
 def mixed_batching(count=256, iters=30, seed=0):
@@ -186,8 +195,12 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.serve_sweep:
-        sweep = [serve_trace(r, args.serve_requests, args.serve_precision, seed=k)
-                 for k, r in enumerate([10, 20, 50, 100, 200, 500])]
+        sweep = []
+        for k, r in enumerate([10, 20, 50, 100, 200, 500]):
+            sweep.append(serve_trace(r, args.serve_requests, args.serve_precision, seed=k,
+                                     schedule=not args.serve_fixed_rho))
+            print(f"rate {r}/s: p50 {sweep[-1]['p50_ms']:.1f} ms, p99 {sweep[-1]['p99_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
         print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
                           "data": "synthetic", "n_gpus": 1}))
         return
@@ -246,7 +259,8 @@ def main():
     }
     batch.close()
     if not args.no_serve:
-        out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision)
+        out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
+                                    schedule=not args.serve_fixed_rho)
     if not args.no_mixed:
         out["mixed_batching"] = mixed_batching()
     if not args.no_cpu_baseline:

@@ -73,6 +73,20 @@ typedef struct {
  * variable (0..4). */
 typedef enum { MATO_FP64 = 0, MATO_FP32 = 1, MATO_BF16_REFINED = 2 } mato_precision;
 
+/* How the x/y/z step of eq. (kkt_step_x) is solved.
+ *   MATO_SOLVE_DENSE     : the precomputed inverse as the method states it, c = K^{-1} [g; b_eq]
+ *                          with the (17n)^2 FP64 inverse (Remarks 1-2), applied as a matrix
+ *                          product in the plan's precision.
+ *   MATO_SOLVE_STRUCTURED: the same c from the block structure of K: A_fc^T A_fc =
+ *                          (n I - 1 1^T) (x) P^T P, whose eigenvalues are 0 on the agent mean
+ *                          and n on the deviations, so that
+ *                              K^{-1} = (1 1^T / n) (x) K_0^{-1} + (I - 1 1^T / n) (x) K_{rho n}^{-1},
+ *                              K_s = [[Pddot^T Pddot + s P^T P, A^T], [A, 0]]  (17 x 17 for n_coef = 11),
+ *                          in per-agent ordering.  Two per-agent inverses replace the dense one;
+ *                          the step runs in FP64 in O(n n_coef^2) per axis.  Not the paper's
+ *                          implementation, the same result up to rounding. */
+typedef enum { MATO_SOLVE_DENSE = 0, MATO_SOLVE_STRUCTURED = 1 } mato_solve_kind;
+
 typedef struct mato_plan_s*   mato_plan;    /* K^{-1} of eq. (kkt_step_x) for one (n, T, basis, rho) */
 typedef struct mato_batch_s*  mato_batch;   /* one or more independent problems iterated together    */
 typedef struct mato_server_s* mato_server;  /* continuous-batching request loop                      */
@@ -104,12 +118,23 @@ mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis,
                                   const double* rhos, int32_t count, int32_t precision,
                                   void* hip_stream, mato_plan* out);
 
-/* Sizes and diagnostics: n, T, n_coef, precision; cond = ||K||_1 ||K^{-1}||_1 (FP64). */
+/* As mato_plan_create_many, with the solve kind (mato_solve_kind).  A structured plan
+ * takes MATO_FP32 (pairwise stage in FP32) or MATO_FP64; BF16_REFINED is INVALID_ARG. */
+mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                const double* rhos, int32_t count, int32_t precision, int32_t solve,
+                                void* hip_stream, mato_plan* out);
+
+/* The plan's mato_solve_kind. */
+mato_status mato_plan_solve_kind(mato_plan plan, int32_t* solve);
+
+/* Sizes and diagnostics: n, T, n_coef, precision; cond = ||K||_1 ||K^{-1}||_1 (FP64)
+ * (structured plans: the larger of the two per-agent estimates). */
 mato_status mato_plan_info(mato_plan plan, int32_t* n, int32_t* T, int32_t* n_coef,
                            int32_t* precision, double* cond);
 
 /* Copies the FP64 inverse of K, (17n x 17n for n_coef = 11) row-major, unknowns ordered
- * [c (agent-major, n*n_coef); nu (agent-major, 6n)], into `kinv` (host or device).  */
+ * [c (agent-major, n*n_coef); nu (agent-major, 6n)], into `kinv` (host or device).
+ * Structured plans expand their two-block form.  */
 mato_status mato_plan_inverse(mato_plan plan, double* kinv);
 
 /* --------------------------------------------------------------- batches ---
@@ -223,6 +248,7 @@ typedef struct {
     double     rho_values[MATO_MAX_STAGES];  /* rho of each stage (replaces rho)          */
     int32_t    rho_start[MATO_MAX_STAGES];   /* first iteration of each stage: 0, then
                                                 increasing multiples of chunk            */
+    int32_t    solve;                        /* mato_solve_kind of every plan             */
 } mato_server_config;
 
 /* Errors: INVALID_ARG (configuration out of range), OUT_OF_MEMORY, HIP. */

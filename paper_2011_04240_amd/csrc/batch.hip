@@ -14,8 +14,10 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
                                 const double* goals, hipStream_t st, BatchImpl<S>** out) {
     auto* B = new BatchImpl<S>();
     B->precision = plans[0]->precision;
+    B->solve = plans[0]->solve;
     B->refine = (B->precision == MATO_FP32) ? 1 : (B->precision == MATO_BF16_REFINED ? 2 : 0);
     if (const char* e = getenv("MATO_REFINE")) B->refine = std::max(0, std::min(kMaxRefine, atoi(e)));
+    if (B->solve == MATO_SOLVE_STRUCTURED) B->refine = 0;     // the structured step is FP64 throughout
     B->stream = st;
     auto fail = [&](mato_status s) { delete B; return s; };
     int agents = 0;
@@ -89,8 +91,8 @@ extern "C" mato_status mato_batch_create(int32_t count, const mato_plan* plans, 
     if (!out || !plans || !starts || !goals || count < 1) { set_error("invalid arguments"); return MATO_ERR_INVALID_ARG; }
     *out = nullptr;
     for (int q = 0; q < count; ++q)
-        if (!plans[q] || plans[q]->precision != plans[0]->precision) {
-            set_error("plan %d is null or of another precision", q);
+        if (!plans[q] || plans[q]->precision != plans[0]->precision || plans[q]->solve != plans[0]->solve) {
+            set_error("plan %d is null or of another precision or solve kind", q);
             return MATO_ERR_INVALID_ARG;
         }
     auto* b = new mato_batch_s();
@@ -338,8 +340,9 @@ extern "C" mato_status mato_batch_set_rho_schedule(mato_batch b, int32_t stages,
                 const mato_plan p = plans[(size_t)j * cnt + q];
                 if (!p || p->n != P.plan->n || p->T != P.plan->T || p->nv != P.plan->nv ||
                     p->t_final != P.plan->t_final || p->precision != P.plan->precision || p->a != P.plan->a ||
-                    p->b != P.plan->b) {
-                    set_error("stage %d plan of problem %d does not match its sizes, basis or precision", j, q);
+                    p->b != P.plan->b || p->solve != P.plan->solve) {
+                    set_error("stage %d plan of problem %d does not match its sizes, basis, precision or solve kind",
+                              j, q);
                     return MATO_ERR_INVALID_ARG;
                 }
             }

@@ -72,6 +72,7 @@ struct ProblemDesc {
     const double* PddtPdd;      // [nv][nv]
     const double* A;            // [6][nv] boundary rows
     const unsigned* pairs;      // [np] pair p -> i | j << 16
+    const double* smat;         // structured solve operands of the plan (nullptr: dense inverse)
     S* lam;                     // [T][3][np] multipliers
     S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
     S* X;                       // [T][3][n]  positions P c of the current coefficients
@@ -138,6 +139,9 @@ struct mato_plan_s {
     double* dPddtPdd = nullptr;
     double* dA = nullptr;        // [6][nv]
     double* dK0c = nullptr;      // [nv][6] c-rows / b_eq-columns of the boundary-only inverse
+    int solve = MATO_SOLVE_DENSE;
+    std::vector<double> Ks0, Ksn;  // structured solve: inverses of K_0 and K_{rho n}, (nv+6)^2 FP64
+    double* dS = nullptr;        // structured solve: [nv][nv] M1, [nv][nv] M2, [nv][6] E0, [nv][6] En
     unsigned* dPairs = nullptr;  // [n(n-1)/2] pair p -> i | j << 16 in the row order of A_fc
     void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 hi or fp64
     void* dAlo = nullptr;        // bf16 lo part

@@ -37,6 +37,8 @@ hipError_t launch_residual(const ProblemDesc<S>*, int, hipStream_t);
 template <typename S>
 hipError_t launch_positions(const ProblemDesc<S>*, int, int, int, hipStream_t);
 template <typename S>
+hipError_t launch_solve_positions(const ProblemDesc<S>*, int, int, hipStream_t);
+template <typename S>
 hipError_t launch_init(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
 template <typename S>
 hipError_t launch_ceq(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
@@ -93,6 +95,7 @@ struct Engine {
     };
 
     int precision = MATO_FP32;
+    int solve = MATO_SOLVE_DENSE;            // every plan of the engine has this solve kind
     int refine = 1;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -249,6 +252,7 @@ struct Engine {
         D.sirho = (S)(1.0 / pl->rho);
         D.P = pl->dP; D.Pdd = pl->dPdd; D.PtP = pl->dPtP; D.PddtPdd = pl->dPddtPdd; D.A = pl->dA;
         D.pairs = pl->dPairs;
+        D.smat = pl->dS;
         D.lam = (S*)(b + P.o_lam);
         D.ssum = (S*)(b + P.o_ssum);
         D.X = (S*)(b + P.o_X);
@@ -335,7 +339,7 @@ struct Engine {
         std::map<mato_plan, std::vector<int>> members;
         std::vector<mato_plan> order;
         for (int q = 0; q < count(); ++q) {
-            if (!probs[q].active) continue;
+            if (!probs[q].active || solve == MATO_SOLVE_STRUCTURED) continue;
             if (!members.count(probs[q].plan)) order.push_back(probs[q].plan);
             members[probs[q].plan].push_back(q);
         }
@@ -522,16 +526,22 @@ struct Engine {
     // --------------------------------------------------------- iterations ---
     hipError_t enqueue_iteration(hipStream_t st, bool events) {
         const int nv = common_nv();
-        hipError_t e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsq, 0, st);
-        if (e != hipSuccess) return e;
-        for (int k = 0; k < refine; ++k) {
-            e = launch_residual<S>(ddesc, count(), st);
+        hipError_t e = hipSuccess;
+        if (solve == MATO_SOLVE_STRUCTURED) {
+            e = launch_solve_positions<S>(ddesc, count(), nv, st);
             if (e != hipSuccess) return e;
-            e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
+        } else {
+            e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsq, 0, st);
+            if (e != hipSuccess) return e;
+            for (int k = 0; k < refine; ++k) {
+                e = launch_residual<S>(ddesc, count(), st);
+                if (e != hipSuccess) return e;
+                e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
+                if (e != hipSuccess) return e;
+            }
+            e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);
             if (e != hipSuccess) return e;
         }
-        e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);
-        if (e != hipSuccess) return e;
         if (events) {
             while ((int)pw_events.size() < pw_used + 2) {
                 hipEvent_t ev;

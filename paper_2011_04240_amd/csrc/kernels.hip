@@ -8,6 +8,8 @@
 //                    S_i(t) = sum_{j>i} b_ij(t) - sum_{j<i} b_ji(t)
 //                    that A_fc^T b reduces to before the factor P^T.
 //   positions_kernel X = P c at every instant and the smoothness cost, once per problem.
+//   solve_positions_kernel  the x/y/z step from the two per-agent inverses of the
+//                    structured solve, then what positions_kernel does.
 //   qbuild_kernel    g = rho A_fc^T b_fc = rho P^T S_i (FP64), plus the iteration's
 //                    residual record and the convergence test.
 //   residual_kernel  FP64 refinement residual g - H c of eq. (kkt_step_x), with
@@ -299,11 +301,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
 // thread owns (axis, agent) columns; the basis rows are staged in LDS in chunks of
 // 32 instants.
 template <typename S, int NV>
-__global__ __launch_bounds__(256) void positions_kernel(const ProblemDesc<S>* __restrict__ probs, int mode) {
-    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
-    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
-    if (!ctrl[3]) return;
-    if (mode == kModeIter && ctrl[1]) return;
+__device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
     const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldc = Dp->ldc;
     gptr<const double> Pm = glob(Dp->P);
     gptr<const double> Pddm = glob(Dp->Pdd);
@@ -355,6 +353,65 @@ __global__ __launch_bounds__(256) void positions_kernel(const ProblemDesc<S>* __
     double z0 = 0.0, z1 = 0.0;
     block_reduce3<double, 256>(z0, cost, z1, red);
     if (threadIdx.x == 0) glob(Dp->misc)[0] = cost;
+}
+
+template <typename S, int NV>
+__global__ __launch_bounds__(256) void positions_kernel(const ProblemDesc<S>* __restrict__ probs, int mode) {
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;
+    if (mode == kModeIter && ctrl[1]) return;
+    positions_body<S, NV>(Dp);
+}
+
+// One workgroup per problem: the x/y/z step of eq. (kkt_step_x) by the block structure
+// of K (structured solve), then X = P c and the cost.  With the agent mean g_mean,
+//     c_i = c_eq,i + M1 g_i + M2 g_mean,   M1 = K_{rho n}^{-1}, M2 = K_0^{-1} - K_{rho n}^{-1}
+// (coefficient rows and columns of the per-agent inverses), all in FP64; the mean is
+// summed over agents in ascending order.
+template <typename S, int NV>
+__global__ __launch_bounds__(256) void solve_positions_kernel(const ProblemDesc<S>* __restrict__ probs) {
+    const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3] || ctrl[1]) return;
+    const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, ldq = Dp->ldq, ldc = Dp->ldc;
+    __shared__ double M[2 * kMaxCoef * kMaxCoef];
+    __shared__ double gm[kAxes * kMaxCoef], h[kAxes * kMaxCoef];
+    gptr<const double> Sm = glob(Dp->smat);
+    for (int e = threadIdx.x; e < 2 * nv * nv; e += blockDim.x) M[e] = Sm[e];
+    gptr<const double> q = glob((const double*)Dp->q);
+    const double inv_n = 1.0 / (double)n;
+    for (int o = threadIdx.x; o < kAxes * nv; o += blockDim.x) {
+        const int a = o / nv, k = o - a * nv;
+        gptr<const double> qa = q + (size_t)a * ldq + k;
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += qa[(size_t)i * nv];
+        gm[o] = s * inv_n;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < kAxes * nv; o += blockDim.x) {
+        const int a = o / nv, k = o - a * nv;
+        double v = 0.0;
+        for (int l = 0; l < nv; ++l) v += M[nv * nv + k * nv + l] * gm[a * nv + l];
+        h[o] = v;
+    }
+    __syncthreads();
+    gptr<double> c = glob(Dp->c);
+    gptr<const double> ceq = glob((const double*)Dp->ceq);
+    for (int col = threadIdx.x; col < kAxes * n; col += blockDim.x) {
+        const int a = col / n, i = col - a * n;
+        gptr<const double> gi = q + (size_t)a * ldq + (size_t)i * nv;
+        const size_t o = (size_t)a * ldc + (size_t)i * nv;
+        double g[NV > 0 ? NV : kMaxCoef];
+        for (int l = 0; l < nv; ++l) g[l] = gi[l];
+        for (int k = 0; k < nv; ++k) {
+            double v = 0.0;
+            for (int l = 0; l < nv; ++l) v += M[k * nv + l] * g[l];
+            c[o + k] = ceq[o + k] + h[a * nv + k] + v;
+        }
+    }
+    __syncthreads();                       // c is read back by other threads of this workgroup
+    positions_body<S, NV>(Dp);
 }
 
 // One workgroup per problem: g = rho P^T S (FP64) into q[a][0 .. n*nv) (and its FP32
@@ -496,9 +553,29 @@ __global__ __launch_bounds__(256) void ceq_kernel(const ProblemDesc<S>* __restri
     if (!ctrl[3]) return;
     const int a = blockIdx.y;
     const int n = Dp->n, nv = Dp->nv, M = n * nv, N = n * (nv + kNb);
-    gptr<const double> K = glob(kinv[blockIdx.x]);
     gptr<const double> beq = glob((const double*)Dp->q) + (size_t)a * Dp->ldq + M;
     gptr<double> ceq = glob(Dp->ceq) + (size_t)a * Dp->ldc;
+    if (Dp->smat) {
+        // structured: c_eq,i = E0 b_mean + En (b_i - b_mean), the b_eq columns of K_0^{-1}, K_{rho n}^{-1}
+        __shared__ double bm[kNb];
+        if (threadIdx.x < kNb) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += beq[(size_t)i * kNb + threadIdx.x];
+            bm[threadIdx.x] = s / (double)n;
+        }
+        __syncthreads();
+        gptr<const double> E0 = glob(Dp->smat) + 2 * nv * nv;
+        gptr<const double> En = E0 + nv * kNb;
+        for (int m = threadIdx.x; m < M; m += blockDim.x) {
+            const int i = m / nv, k = m - i * nv;
+            double v = 0.0;
+            for (int r = 0; r < kNb; ++r)
+                v += E0[k * kNb + r] * bm[r] + En[k * kNb + r] * (beq[(size_t)i * kNb + r] - bm[r]);
+            ceq[m] = v;
+        }
+        return;
+    }
+    gptr<const double> K = glob(kinv[blockIdx.x]);
     for (int m = threadIdx.x; m < M; m += blockDim.x) {
         gptr<const double> row = K + (size_t)m * N + M;
         double v = 0.0;
@@ -627,6 +704,16 @@ hipError_t launch_ceq(const ProblemDesc<S>* probs, const double* const* kinv, in
 }
 
 template <typename S>
+hipError_t launch_solve_positions(const ProblemDesc<S>* probs, int nprob, int nv, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    if (nv == 11)
+        solve_positions_kernel<S, 11><<<nprob, 256, 0, st>>>(probs);
+    else
+        solve_positions_kernel<S, 0><<<nprob, 256, 0, st>>>(probs);
+    return hipGetLastError();
+}
+
+template <typename S>
 hipError_t launch_init(const ProblemDesc<S>* probs, const double* const* k0c, int nprob, hipStream_t st) {
     if (nprob <= 0) return hipSuccess;
     init_kernel<S><<<nprob, 256, 0, st>>>(probs, k0c);
@@ -645,6 +732,8 @@ template hipError_t launch_residual<float>(const ProblemDesc<float>*, int, hipSt
 template hipError_t launch_residual<double>(const ProblemDesc<double>*, int, hipStream_t);
 template hipError_t launch_ceq<float>(const ProblemDesc<float>*, const double* const*, int, hipStream_t);
 template hipError_t launch_ceq<double>(const ProblemDesc<double>*, const double* const*, int, hipStream_t);
+template hipError_t launch_solve_positions<float>(const ProblemDesc<float>*, int, int, hipStream_t);
+template hipError_t launch_solve_positions<double>(const ProblemDesc<double>*, int, int, hipStream_t);
 template hipError_t launch_init<float>(const ProblemDesc<float>*, const double* const*, int, hipStream_t);
 template hipError_t launch_init<double>(const ProblemDesc<double>*, const double* const*, int, hipStream_t);
 

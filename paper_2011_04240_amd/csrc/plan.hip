@@ -98,6 +98,26 @@ __global__ void assemble_kkt(double* __restrict__ W, int n, int nv, int nb, doub
     }
 }
 
+// Augmented [[Pdd^T Pdd + sigma P^T P, A^T], [A, 0] | I] of one agent and axis
+// ((nv + nb) x 2(nv + nb)), matrix blockIdx.y of a stack with stride ms and
+// shift sigma[blockIdx.y].
+__global__ void assemble_agent_kkt(double* __restrict__ W, int nv, int nb, const double* __restrict__ sigma,
+                                   size_t ms, const double* __restrict__ PtP,
+                                   const double* __restrict__ PddtPdd, const double* __restrict__ A) {
+    const int N = nv + nb;
+    double* Wm = W + ms * blockIdx.y;
+    const double sg = sigma[blockIdx.y];
+    for (int e = threadIdx.x; e < N * 2 * N; e += blockDim.x) {
+        const int r = e / (2 * N), c = e % (2 * N);
+        double v = 0.0;
+        if (c >= N) v = (c - N == r) ? 1.0 : 0.0;
+        else if (r < nv && c < nv) v = PddtPdd[r * nv + c] + sg * PtP[r * nv + c];
+        else if (r < nv) v = A[(c - nv) * nv + r];
+        else if (c < nv) v = A[(r - nv) * nv + c];
+        Wm[e] = v;
+    }
+}
+
 // Column absolute sums of the left half (for ||K||_1) or of the right half; matrix
 // blockIdx.y of a stack with stride ms.
 __global__ void column_abs_sums(const double* __restrict__ W, int N, int off, size_t ms, double* __restrict__ out) {
@@ -311,34 +331,69 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         MATO_TRY(upload(&p->dPairs, pairs, &p->bytes));
     }
 
-    // boundary-only minimum-acceleration KKT (initialisation): [[Pdd^T Pdd, A^T], [A, 0]]
+    // Per-agent KKT matrices K_sigma = [[Pdd^T Pdd + sigma P^T P, A^T], [A, 0]].  K_0 is the
+    // boundary-only minimum-acceleration problem (initialisation).  With the structured
+    // solve also K_{rho n} for every rho: the complete-graph Laplacian n I - 1 1^T has the
+    // eigenvalue 0 on the agent mean and n on every deviation from it, so
+    //     K^{-1} = (1 1^T / n) (x) K_0^{-1} + (I - 1 1^T / n) (x) K_{rho n}^{-1}
+    // in per-agent ordering, and c_i = K_0^{-1} [g_mean; b_mean] + K_{rho n}^{-1} [g_i - g_mean; b_i - b_mean].
+    const bool structured = p0->solve == MATO_SOLVE_STRUCTURED;
     {
-        const int N0 = nv + nb;
-        std::vector<double> zeros(nv * nv, 0.0);
-        double *W0 = nullptr, *inv0 = nullptr, *dzero = nullptr;
-        MATO_HIP(hipMalloc(&W0, sizeof(double) * N0 * 2 * N0));
-        MATO_HIP(hipMalloc(&inv0, sizeof(double) * N0 * N0));
-        MATO_HIP(hipMalloc(&dzero, sizeof(double) * nv * nv));
-        MATO_HIP(hipMemcpy(dzero, zeros.data(), sizeof(double) * nv * nv, hipMemcpyHostToDevice));
-        // n = 1, rho = 0: H = Pdd^T Pdd
-        assemble_kkt<<<grid_for((size_t)N0 * 2 * N0, 256), 256, 0, st>>>(W0, 1, nv, nb, 0.0, dzero,
-                                                                         p0->dPddtPdd, p0->dA);
-        double c0 = 0.0;
-        mato_status s = gauss_jordan(W0, N0, 1, &inv0, &c0, st);
-        if (s == MATO_OK) {
-            std::vector<double> h((size_t)N0 * N0);
+        const int N0 = nv + nb, m0 = structured ? cnt + 1 : 1;
+        const size_t ms0 = (size_t)N0 * 2 * N0;
+        std::vector<double> sig(m0, 0.0);
+        for (int m = 1; m < m0; ++m) sig[m] = ps[m - 1]->rho * n;
+        double *W0 = nullptr, *inv0 = nullptr, *dsig = nullptr;
+        MATO_HIP(hipMalloc(&W0, sizeof(double) * ms0 * m0));
+        MATO_HIP(hipMalloc(&inv0, sizeof(double) * N0 * N0 * m0));
+        MATO_HIP(hipMalloc(&dsig, sizeof(double) * m0));
+        MATO_HIP(hipMemcpy(dsig, sig.data(), sizeof(double) * m0, hipMemcpyHostToDevice));
+        assemble_agent_kkt<<<dim3(1, m0), 256, 0, st>>>(W0, nv, nb, dsig, ms0, p0->dPtP, p0->dPddtPdd, p0->dA);
+        std::vector<double*> invs(m0);
+        for (int m = 0; m < m0; ++m) invs[m] = inv0 + (size_t)N0 * N0 * m;
+        std::vector<double> conds(m0, 0.0);
+        mato_status s = gauss_jordan(W0, N0, m0, invs.data(), conds.data(), st);
+        std::vector<double> h((size_t)N0 * N0 * m0);
+        if (s == MATO_OK)
             MATO_HIP(hipMemcpy(h.data(), inv0, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
-            p0->K0inv_c.assign((size_t)nv * nb, 0.0);
-            for (int r = 0; r < nv; ++r)
-                for (int b = 0; b < nb; ++b) p0->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
-        }
         dfree(W0);
         dfree(inv0);
-        dfree(dzero);
+        dfree(dsig);
         if (s != MATO_OK) return s;
+        p0->K0inv_c.assign((size_t)nv * nb, 0.0);
+        for (int r = 0; r < nv; ++r)
+            for (int b = 0; b < nb; ++b) p0->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
         for (auto p : ps) {
             if (p != p0) p->K0inv_c = p0->K0inv_c;
             MATO_TRY(upload(&p->dK0c, p->K0inv_c, &p->bytes));
+        }
+        if (structured) {
+            for (int m = 0; m < cnt; ++m) {
+                mato_plan p = ps[m];
+                const double* K0i = h.data();
+                const double* Kni = h.data() + (size_t)N0 * N0 * (m + 1);
+                p->Ks0.assign(K0i, K0i + (size_t)N0 * N0);
+                p->Ksn.assign(Kni, Kni + (size_t)N0 * N0);
+                p->cond = std::max(conds[0], conds[m + 1]);
+                std::vector<double> S((size_t)2 * nv * nv + (size_t)2 * nv * nb);
+                double* M1 = S.data();
+                double* M2 = M1 + nv * nv;
+                double* E0 = M2 + nv * nv;
+                double* En = E0 + nv * nb;
+                for (int r = 0; r < nv; ++r) {
+                    for (int c = 0; c < nv; ++c) {
+                        M1[r * nv + c] = Kni[(size_t)r * N0 + c];
+                        M2[r * nv + c] = K0i[(size_t)r * N0 + c] - Kni[(size_t)r * N0 + c];
+                    }
+                    for (int b = 0; b < nb; ++b) {
+                        E0[r * nb + b] = K0i[(size_t)r * N0 + nv + b];
+                        En[r * nb + b] = Kni[(size_t)r * N0 + nv + b];
+                    }
+                }
+                MATO_TRY(upload(&p->dS, S, &p->bytes));
+            }
+            MATO_HIP(hipStreamSynchronize(st));
+            return MATO_OK;
         }
     }
 
@@ -408,6 +463,7 @@ extern "C" void mato_plan_destroy(mato_plan p) {
     dfree(p->dPairs);
     dfree(p->dAhi);
     dfree(p->dAlo);
+    dfree(p->dS);
     delete p;
 }
 
@@ -431,12 +487,20 @@ static mato_status check_plan_args(int32_t n, int32_t T, const mato_basis* basis
     return MATO_OK;
 }
 
-extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
-                                             const double* rhos, int32_t count, int32_t precision,
-                                             void* hip_stream, mato_plan* out) {
+extern "C" mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                           const double* rhos, int32_t count, int32_t precision, int32_t solve,
+                                           void* hip_stream, mato_plan* out) {
     if (!out || !rhos || count < 1) { set_error("null argument or count < 1"); return MATO_ERR_INVALID_ARG; }
     for (int m = 0; m < count; ++m) out[m] = nullptr;
     MATO_TRY(check_plan_args(n, T, basis, a, b, precision));
+    if (solve != MATO_SOLVE_DENSE && solve != MATO_SOLVE_STRUCTURED) {
+        set_error("unknown solve kind %d", solve);
+        return MATO_ERR_INVALID_ARG;
+    }
+    if (solve == MATO_SOLVE_STRUCTURED && precision == MATO_BF16_REFINED) {
+        set_error("the structured solve has no BF16 product: use MATO_FP32 or MATO_FP64");
+        return MATO_ERR_INVALID_ARG;
+    }
     for (int m = 0; m < count; ++m)
         if (!(rhos[m] > 0) || !std::isfinite(rhos[m])) { set_error("rho must be finite and > 0"); return MATO_ERR_INVALID_ARG; }
     int device = 0;
@@ -449,6 +513,7 @@ extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_ba
         mato_plan p = new mato_plan_s();
         p->n = n; p->T = T; p->nv = basis->n_coef; p->nb = kNb; p->precision = precision;
         p->t_final = basis->t_final; p->a = a; p->b = b; p->rho = rhos[m]; p->cond = 0.0;
+        p->solve = solve;
         p->stream = (hipStream_t)hip_stream;
         p->device = device;
         ps.push_back(p);
@@ -460,6 +525,12 @@ extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_ba
     }
     for (int m = 0; m < count; ++m) out[m] = ps[m];
     return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
+                                             const double* rhos, int32_t count, int32_t precision,
+                                             void* hip_stream, mato_plan* out) {
+    return mato_plan_create_ex(n, T, basis, a, b, rhos, count, precision, MATO_SOLVE_DENSE, hip_stream, out);
 }
 
 extern "C" mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis, double a,
@@ -485,8 +556,35 @@ extern "C" mato_status mato_plan_info(mato_plan p, int32_t* n, int32_t* T, int32
 
 extern "C" mato_status mato_plan_inverse(mato_plan p, double* kinv) {
     if (!p || !kinv) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
-    const size_t N = (size_t)p->n * (p->nv + p->nb);
-    MATO_HIP(hipMemcpyAsync(kinv, p->dKinv, sizeof(double) * N * N, hipMemcpyDefault, p->stream));
+    const int n = p->n, nv = p->nv, nb = p->nb, N0 = nv + nb;
+    const size_t N = (size_t)n * N0;
+    if (p->solve == MATO_SOLVE_STRUCTURED) {
+        // the two-block form, expanded into the ordering [c (agent-major); nu (agent-major)]
+        std::vector<double> h(N * N);
+        auto split = [&](size_t R, int* agent, int* local) {
+            if (R < (size_t)n * nv) { *agent = (int)(R / nv); *local = (int)(R % nv); }
+            else { const size_t u = R - (size_t)n * nv; *agent = (int)(u / nb); *local = nv + (int)(u % nb); }
+        };
+        for (size_t R = 0; R < N; ++R) {
+            int i, kr;
+            split(R, &i, &kr);
+            for (size_t C = 0; C < N; ++C) {
+                int j, kc;
+                split(C, &j, &kc);
+                const double e0 = p->Ks0[(size_t)kr * N0 + kc], en = p->Ksn[(size_t)kr * N0 + kc];
+                h[R * N + C] = e0 / n + ((i == j ? 1.0 : 0.0) - 1.0 / n) * en;
+            }
+        }
+        MATO_HIP(hipMemcpyAsync(kinv, h.data(), sizeof(double) * N * N, hipMemcpyDefault, p->stream));
+    } else {
+        MATO_HIP(hipMemcpyAsync(kinv, p->dKinv, sizeof(double) * N * N, hipMemcpyDefault, p->stream));
+    }
     MATO_HIP(hipStreamSynchronize(p->stream));
+    return MATO_OK;
+}
+
+extern "C" mato_status mato_plan_solve_kind(mato_plan p, int32_t* solve) {
+    if (!p || !solve) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    *solve = p->solve;
     return MATO_OK;
 }

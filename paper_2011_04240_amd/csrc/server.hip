@@ -45,7 +45,9 @@ struct mato_server_s {
 
 namespace mato {
 
-static size_t plan_bytes_estimate(int n, int nv, int T, int precision) {
+static size_t plan_bytes_estimate(int n, int nv, int T, int precision, int solve) {
+    if (solve == MATO_SOLVE_STRUCTURED)
+        return (size_t)T * nv * 16 + (size_t)nv * (4 * nv + 4 * kNb) * 8 + (size_t)n * n * 2 + 4096;
     const size_t N = (size_t)n * (nv + kNb), M = (size_t)n * nv;
     const size_t Mp = (size_t)round_up((int)M, 64), ldk = (size_t)round_up((int)M, 32);
     const size_t op = precision == MATO_FP64 ? 8 : (precision == MATO_BF16_REFINED ? 4 : 4);
@@ -122,11 +124,12 @@ struct ServerOps {
                 auto it = s->plans.find(n * kMaxStages + j);
                 if (it != s->plans.end()) keep.push_back(it->second);
             }
-            const size_t est = missing.size() * plan_bytes_estimate(n, s->cfg.basis.n_coef, s->cfg.T, s->cfg.precision);
+            const size_t est = missing.size() * plan_bytes_estimate(n, s->cfg.basis.n_coef, s->cfg.T, s->cfg.precision,
+                                                                       s->cfg.solve);
             if (!make_room(s, est, keep, -1)) return MATO_OK;     // not now: wait for memory
             std::vector<mato_plan> made(missing.size(), nullptr);
-            MATO_TRY(mato_plan_create_many(n, s->cfg.T, &s->cfg.basis, s->cfg.a, s->cfg.b, rhos.data(),
-                                           (int)rhos.size(), s->cfg.precision, s->stream, made.data()));
+            MATO_TRY(mato_plan_create_ex(n, s->cfg.T, &s->cfg.basis, s->cfg.a, s->cfg.b, rhos.data(),
+                                         (int)rhos.size(), s->cfg.precision, s->cfg.solve, s->stream, made.data()));
             for (size_t m = 0; m < missing.size(); ++m) s->plans[n * kMaxStages + missing[m]] = made[m];
         }
         for (int j = 0; j < stages(s); ++j) out->push_back(s->plans[n * kMaxStages + j]);
@@ -237,6 +240,8 @@ struct ServerOps {
         e->precision = s->cfg.precision;
         e->refine = (e->precision == MATO_FP32) ? 1 : (e->precision == MATO_BF16_REFINED ? 2 : 0);
         if (const char* v = getenv("MATO_REFINE")) e->refine = std::max(0, std::min(kMaxRefine, atoi(v)));
+        e->solve = s->cfg.solve;
+        if (e->solve == MATO_SOLVE_STRUCTURED) e->refine = 0;
         e->stream = s->stream;
         e->tol = s->cfg.tol;
         MATO_TRY(e->init_capacity(s->cfg.max_slots));
@@ -265,7 +270,9 @@ extern "C" mato_status mato_server_create(const mato_server_config* cfg, void* h
     if (cfg->max_slots < 1 || cfg->chunk < 1 || cfg->max_iters < 1 || cfg->T < cfg->basis.n_coef ||
         !(cfg->a > 0) || !(cfg->b > 0) || !(cfg->rho > 0) || !(cfg->basis.t_final > 0) ||
         (cfg->precision != MATO_FP64 && cfg->precision != MATO_FP32 && cfg->precision != MATO_BF16_REFINED) ||
-        (cfg->projection != 0 && cfg->projection != 1) || cfg->rho_stages < 0 || cfg->rho_stages > kMaxStages) {
+        (cfg->projection != 0 && cfg->projection != 1) || cfg->rho_stages < 0 || cfg->rho_stages > kMaxStages ||
+        (cfg->solve != MATO_SOLVE_DENSE && cfg->solve != MATO_SOLVE_STRUCTURED) ||
+        (cfg->solve == MATO_SOLVE_STRUCTURED && cfg->precision == MATO_BF16_REFINED)) {
         set_error("invalid server configuration");
         return MATO_ERR_INVALID_ARG;
     }

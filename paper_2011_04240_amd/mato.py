@@ -29,6 +29,8 @@ MATO_MAX_STAGES = 16
 
 MATO_FP64, MATO_FP32, MATO_BF16_REFINED = 0, 1, 2
 PRECISIONS = {"fp64": MATO_FP64, "fp32": MATO_FP32, "bf16": MATO_BF16_REFINED}
+MATO_SOLVE_DENSE, MATO_SOLVE_STRUCTURED = 0, 1
+SOLVES = {"dense": MATO_SOLVE_DENSE, "structured": MATO_SOLVE_STRUCTURED}
 
 
 class MatoError(RuntimeError):
@@ -46,7 +48,7 @@ class ServerConfig(ctypes.Structure):
                 ("rho", ctypes.c_double), ("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_double), ("chunk", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("projection", ctypes.c_int32), ("rho_stages", ctypes.c_int32),
-                ("rho_values", ctypes.c_double * 16), ("rho_start", ctypes.c_int32 * 16)]
+                ("rho_values", ctypes.c_double * 16), ("rho_start", ctypes.c_int32 * 16), ("solve", ctypes.c_int32)]
 
 
 _lib = None
@@ -60,6 +62,9 @@ SIGNATURES = {
     "mato_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _f64, _i32, _vp, _pvp]),
     "mato_plan_destroy": (None, [_vp]),
     "mato_plan_create_many": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _pf64, _i32, _i32, _vp, _pvp]),
+    "mato_plan_create_ex": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _pf64, _i32, _i32, _i32, _vp,
+                                   _pvp]),
+    "mato_plan_solve_kind": (_i32, [_vp, _pi32]),
     "mato_plan_info": (_i32, [_vp, _pi32, _pi32, _pi32, _pi32, _pf64]),
     "mato_plan_inverse": (_i32, [_vp, _vp]),
     "mato_batch_create": (_i32, [_i32, _pvp, _vp, _vp, _vp, _pvp]),
@@ -160,6 +165,21 @@ def mato_plan_create_many(n, T, n_coef, t_final, a, b, rhos, precision, stream=N
     _check(lib().mato_plan_create_many(n, T, ctypes.byref(basis), a, b, r, len(rhos), precision,
                                        _stream_ptr(stream), out))
     return [ctypes.c_void_p(x) for x in out]
+
+
+def mato_plan_create_ex(n, T, n_coef, t_final, a, b, rhos, precision, solve, stream=None):
+    out = (ctypes.c_void_p * len(rhos))()
+    r = (ctypes.c_double * len(rhos))(*rhos)
+    basis = _Basis(0, n_coef, t_final)
+    _check(lib().mato_plan_create_ex(n, T, ctypes.byref(basis), a, b, r, len(rhos), precision, solve,
+                                     _stream_ptr(stream), out))
+    return [ctypes.c_void_p(x) for x in out]
+
+
+def mato_plan_solve_kind(plan):
+    v = _i32()
+    _check(lib().mato_plan_solve_kind(plan, ctypes.byref(v)))
+    return v.value
 
 
 def mato_plan_destroy(plan):
@@ -326,19 +346,23 @@ class Plan:
     """K^{-1} of the x/y/z step for one (n, T, basis, rho); a, b are the spheroid dimensions."""
 
     def __init__(self, n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", stream=None,
-                 handle=None):
+                 handle=None, solve="dense"):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.solve = SOLVES[solve] if isinstance(solve, str) else int(solve)
         self.n, self.T, self.n_coef = n, T, n_coef
         self.t_final, self.a, self.b, self.rho = t_final, a, b, rho
-        self.handle = handle if handle is not None else mato_plan_create(n, T, n_coef, t_final, a, b, rho,
-                                                                          self.precision, stream)
+        if handle is None:
+            handle = mato_plan_create_ex(n, T, n_coef, t_final, a, b, [rho], self.precision, self.solve, stream)[0]
+        self.handle = handle
 
     @classmethod
-    def schedule(cls, n, T, rhos, n_coef=11, t_final=10.0, a=0.3, b=0.6, precision="fp32", stream=None):
+    def schedule(cls, n, T, rhos, n_coef=11, t_final=10.0, a=0.3, b=0.6, precision="fp32", stream=None,
+                 solve="dense"):
         """Plans for several rho (a rho schedule), inverted together."""
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        hs = mato_plan_create_many(n, T, n_coef, t_final, a, b, list(rhos), pr, stream)
-        return [cls(n, T, n_coef, t_final, a, b, r, pr, handle=h) for r, h in zip(rhos, hs)]
+        sv = SOLVES[solve] if isinstance(solve, str) else int(solve)
+        hs = mato_plan_create_ex(n, T, n_coef, t_final, a, b, list(rhos), pr, sv, stream)
+        return [cls(n, T, n_coef, t_final, a, b, r, pr, handle=h, solve=sv) for r, h in zip(rhos, hs)]
 
     @property
     def scalar(self):
@@ -370,11 +394,12 @@ class Server:
 
     def __init__(self, T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", max_slots=64,
                  hbm_budget_bytes=0.0, chunk=10, max_iters=2000, tol=1e-3, shifted=False, rho_schedule=None,
-                 stream=None):
+                 stream=None, solve="dense"):
         self.T, self.n_coef = T, n_coef
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = ServerConfig(T, _Basis(0, n_coef, t_final), a, b, rho, self.precision, max_slots, hbm_budget_bytes,
                            chunk, max_iters, tol, int(bool(shifted)))
+        cfg.solve = SOLVES[solve] if isinstance(solve, str) else int(solve)
         if rho_schedule is not None:
             values, starts = rho_schedule
             cfg.rho_stages = len(values)

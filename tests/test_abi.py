@@ -62,3 +62,22 @@ def test_null_handles_are_rejected():
     assert L.mato_batch_step(None, 1, 0.0, 0) == mato.MATO_ERR_INVALID_ARG
     assert L.mato_plan_info(None, None, None, None, None, None) == mato.MATO_ERR_INVALID_ARG
     assert L.mato_batch_create(0, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == mato.MATO_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("precision,solve", [
+    (mato.MATO_BF16_REFINED, mato.MATO_SOLVE_STRUCTURED),   # no BF16 product in the structured step
+    (mato.MATO_FP32, 2),                                     # unknown solve kind
+])
+def test_solve_kind_validation(precision, solve):
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_plan_create_ex(4, 50, 11, 5.0, 0.4, 0.8, [1.0], precision, solve)
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
+
+
+def test_server_rejects_structured_bf16():
+    cfg = mato.ServerConfig(100, mato._Basis(0, 11, 10.0), 0.3, 0.6, 1.0, mato.MATO_BF16_REFINED, 4, 0.0, 10,
+                            100, 1e-3, 0)
+    cfg.solve = mato.MATO_SOLVE_STRUCTURED
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_server_create(cfg)
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG

@@ -42,8 +42,8 @@ def _oracle_plan(c):
     return am.make_plan(c["n"], c["T"], 11, c["tf"], c["a"], c["b"], 1.0)
 
 
-def _gpu_plan(c, precision):
-    return mato.Plan(c["n"], c["T"], 11, c["tf"], c["a"], c["b"], 1.0, precision)
+def _gpu_plan(c, precision, solve="dense"):
+    return mato.Plan(c["n"], c["T"], 11, c["tf"], c["a"], c["b"], 1.0, precision, solve=solve)
 
 
 @pytest.mark.parametrize("name", ["swap_circle_n4_T50", "swap_sphere_n16_T100", "box_n37_T53_ragged"])
@@ -74,7 +74,7 @@ def test_initial_state_matches_oracle(precision):
     assert rel(b.linear_term(0), g_ref) < tol
 
 
-def _single_step(name, precision, k_oracle=5, shifted=False):
+def _single_step(name, precision, k_oracle=5, shifted=False, solve="dense"):
     c = CASES[name]
     s, g = c["gen"]()
     op = _oracle_plan(c)
@@ -88,7 +88,7 @@ def _single_step(name, precision, k_oracle=5, shifted=False):
     ref = am.iterate_rhs(op, b_fc, lam.astype(np.float64), st.beq, shifted)
     g_next = am.linear_term(op, ref["proj"] - ref["lam"] / op.rho)
 
-    gp = _gpu_plan(c, precision)
+    gp = _gpu_plan(c, precision, solve)
     bt = mato.Batch([gp], [s], [g])
     bt.set_state(0, st.c, lam, proj)
     if shifted:
@@ -207,3 +207,66 @@ def test_tiles_do_not_change_iterates():
     for o in outs[1:]:
         np.testing.assert_array_equal(o["c"], outs[0]["c"])
         np.testing.assert_array_equal(o["lam"], outs[0]["lam"])
+
+
+# ------------------------------------------------------------ structured solve ---
+@pytest.mark.parametrize("name", ["swap_circle_n4_T50", "swap_sphere_n16_T100", "box_n37_T53_ragged"])
+def test_structured_inverse_matches_oracle(name):
+    """The two-block form of K^{-1} expanded to (17n)^2 equals the oracle's dense inverse."""
+    c = CASES[name]
+    say("structured inverse", name)
+    gp = _gpu_plan(c, "fp64", "structured")
+    assert mato.mato_plan_solve_kind(gp.handle) == mato.MATO_SOLVE_STRUCTURED
+    assert rel(gp.inverse(), _oracle_plan(c).Kinv) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["swap_circle_n4_T50", "swap_sphere_n16_T100", "box_n37_T53_ragged", "box_n64_T100"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_single_step_parity_structured(name, precision):
+    say("single step structured", name, precision)
+    errs = _single_step(name, precision, solve="structured")
+    say("  errors", {k: "%.2e" % v for k, v in errs.items()})
+    tol = 1e-8 if precision == "fp64" else 1e-5
+    for k, v in errs.items():
+        assert v < tol, (k, v, errs)
+
+
+def test_full_run_structured_fp64_swap_circle():
+    c = CASES["swap_circle_n4_T50"]
+    say("full run structured fp64 n4")
+    s, g = c["gen"]()
+    st = am.solve(_oracle_plan(c), s, g, 200)
+    bt = mato.Batch([_gpu_plan(c, "fp64", "structured")], [s], [g])
+    bt.run(200, 0.0, 50)
+    r_max, r_rms, cost = bt.residuals(0)
+    assert len(r_max) == 200
+    assert rel(r_max, st.history["r_max"]) < 1e-8
+    assert rel(cost, st.history["cost"]) < 1e-10
+    assert rel(bt.coeffs(0), st.c) < 1e-9
+
+
+def test_structured_and_dense_runs_agree_fp64():
+    """n = 37, T = 53 (ragged), 120 iterations: the two solves differ only by rounding."""
+    c = CASES["box_n37_T53_ragged"]
+    say("structured vs dense fp64 n37")
+    s, g = c["gen"]()
+    out = []
+    for solve in ("dense", "structured"):
+        bt = mato.Batch([_gpu_plan(c, "fp64", solve)], [s], [g])
+        bt.run(120, 0.0, 40)
+        out.append((bt.coeffs(0), bt.residuals(0)))
+    assert rel(out[1][0], out[0][0]) < 1e-8
+    assert rel(out[1][1][0], out[0][1][0]) < 1e-6
+
+
+def test_structured_graph_and_eager_agree_bitwise():
+    c = CASES["box_n37_T53_ragged"]
+    say("structured graph vs eager")
+    s, g = c["gen"]()
+    b1 = mato.Batch([_gpu_plan(c, "fp32", "structured")], [s], [g])
+    b2 = mato.Batch([_gpu_plan(c, "fp32", "structured")], [s], [g])
+    b1.step(37, use_graph=True)
+    b2.step(37, use_graph=False)
+    s1, s2 = b1.get_state(0), b2.get_state(0)
+    np.testing.assert_array_equal(s1["c"], s2["c"])
+    np.testing.assert_array_equal(s1["lam"], s2["lam"])
