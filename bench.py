@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the served-latency sweep over arrival rates 10..500 /s")
-    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--serve-solve", default="structured", choices=["dense", "structured"])
+    ap.add_argument("--sweep-requests", type=int, default=2000,
+                    help="requests per rate in the sweep (fewer where the trace would exceed 90 s)")
     ap.add_argument("--serve-fixed-rho", action="store_true",
                     help="serve with one rho instead of the increasing schedule")
     return ap.parse_args()
@@ -109,7 +112,7 @@ RHO_SCHEDULE = ([2.0 ** j for j in range(10)], [30 * j for j in range(10)])
 
 
 def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_iters=2000, tol=1e-3,
-                schedule=True):
+                schedule=True, solve="structured"):
     """Poisson arrivals of random-box problems (n uniform over 4..128, box at the n=64
     density) replayed in real time through the server; latency = finish - arrival.
     With `schedule`, ten increasing rho (doubling every 30 iterations, Sec. IV-A)."""
@@ -121,7 +124,7 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
     arr = sc.poisson_arrivals(rate, count, seed=seed)
     srv = mato.Server(T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision=precision,
                       max_slots=max_slots, chunk=chunk, max_iters=max_iters, tol=tol,
-                      rho_schedule=RHO_SCHEDULE if schedule else None)
+                      rho_schedule=RHO_SCHEDULE if schedule else None, solve=solve)
     t0 = time.perf_counter()
     srv.warm(4, 128)
     warm_s = time.perf_counter() - t0
@@ -133,8 +136,29 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
             "throughput_problems_per_s": count / wall, "updates_per_s": upd / wall,
             "converged_frac": float(np.mean(conv)), "capped_frac": float(np.mean(its >= max_iters)),
             "mean_iters": float(np.mean(its)), "wall_s": wall, "plan_warm_s": warm_s,
-            "precision": precision, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol,
+            "precision": precision, "solve": solve, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol,
             "rho": ({"values": RHO_SCHEDULE[0], "start_iter": RHO_SCHEDULE[1]} if schedule else 1.0)}
+
+
+def structured_step(n, T, B, starts, goals, args):
+    """The same step with the structured x/y/z solve (two per-agent inverses, FP64)."""
+    import torch
+    from paper_2011_04240_amd import mato
+    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, "fp32", solve="structured")
+    batch = mato.Batch([plan] * B, starts, goals)
+    if not args.no_autotune:
+        batch.autotune()
+    batch.step(args.warmup, use_graph=False)
+    batch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps, use_graph=False)
+    batch.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    batch.close()
+    upd = n * (n - 1) // 2 * T * B * args.steps
+    return {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": upd / wall, "precision": "fp32"}
 
 
 def mixed_batching(count=256, iters=30, seed=0):
@@ -153,6 +177,17 @@ def mixed_batching(count=256, iters=30, seed=0):
     batch.step(iters, use_graph=True)
     batch.sync()
     t_batch = time.perf_counter() - t0
+    batch.close()
+    splans = {n: mato.Plan(n, 100, 11, 10.0, 0.3, 0.6, 1.0, "fp32", solve="structured") for n in sorted(set(ns))}
+    sbatch = mato.Batch([splans[n] for n in ns], [x[0] for x in scen], [x[1] for x in scen])
+    sbatch.set_tiles(*tiles)
+    sbatch.step(3)
+    sbatch.sync()
+    t0 = time.perf_counter()
+    sbatch.step(iters, use_graph=True)
+    sbatch.sync()
+    t_struct = time.perf_counter() - t0
+    sbatch.close()
     solo = [mato.Batch([plans[n]], [scen[k][0]], [scen[k][1]]) for k, n in enumerate(ns)]
     for b in solo:
         b.step(1, use_graph=False)
@@ -168,6 +203,8 @@ def mixed_batching(count=256, iters=30, seed=0):
             "batched": {"ms_per_iter": t_batch / iters * 1e3, "updates_per_s": upd / t_batch,
                         "problems_per_s_300_iters": count / (t_batch / iters * 300),
                         "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]}},
+            "batched_structured": {"ms_per_iter": t_struct / iters * 1e3, "updates_per_s": upd / t_struct,
+                                   "problems_per_s_300_iters": count / (t_struct / iters * 300)},
             "per_problem": {"ms_per_iter_all": t_solo / iters * 1e3, "updates_per_s": upd / t_solo,
                             "problems_per_s_300_iters": count / (t_solo / iters * 300)},
             "speedup": t_solo / t_batch}
@@ -197,8 +234,8 @@ def main():
     if args.serve_sweep:
         sweep = []
         for k, r in enumerate([10, 20, 50, 100, 200, 500]):
-            sweep.append(serve_trace(r, args.serve_requests, args.serve_precision, seed=k,
-                                     schedule=not args.serve_fixed_rho))
+            sweep.append(serve_trace(r, min(args.sweep_requests, int(r * 90)), args.serve_precision, seed=k,
+                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve))
             print(f"rate {r}/s: p50 {sweep[-1]['p50_ms']:.1f} ms, p99 {sweep[-1]['p99_ms']:.1f} ms",
                   file=sys.stderr, flush=True)
         print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
@@ -258,9 +295,10 @@ def main():
         "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
     }
     batch.close()
+    out["structured_step"] = structured_step(n, T, B, starts, goals, args)
     if not args.no_serve:
         out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
-                                    schedule=not args.serve_fixed_rho)
+                                    schedule=not args.serve_fixed_rho, solve=args.serve_solve)
     if not args.no_mixed:
         out["mixed_batching"] = mixed_batching()
     if not args.no_cpu_baseline:
