@@ -153,3 +153,39 @@ def test_autotune_keeps_results():
     tuned.step(10)
     for q in range(2):
         np.testing.assert_array_equal(ref.get_state(q)["lam"], tuned.get_state(q)["lam"])
+
+
+def test_fp64_lds_limit():
+    """FP64 keeps 3 (n + n(n-1)/2) doubles per instant in LDS: n = 116 does not fit."""
+    say("fp64 lds limit")
+    s, g = sc.random_density_box(116, seed=5)
+    p = mato.Plan(116, 12, 11, 2.0, 0.3, 0.6, 1.0, "fp64", solve="structured")
+    with pytest.raises(mato.MatoError) as e:
+        mato.Batch([p], [s], [g])
+    assert e.value.status == mato.MATO_ERR_UNSUPPORTED
+
+
+def test_fp64_largest_n_matches_oracle():
+    say("fp64 n115")
+    n, T = 115, 12
+    s, g = sc.random_density_box(n, seed=6)
+    ref = am.solve(am.make_plan(n, T, 11, 2.0, 0.3, 0.6, 1.0), s, g, 3)
+    b = mato.Batch([mato.Plan(n, T, 11, 2.0, 0.3, 0.6, 1.0, "fp64", solve="structured")], [s], [g])
+    b.step(3, use_graph=False)
+    r_max, _, _ = b.residuals(0)
+    assert rel(b.coeffs(0), ref.c) < 1e-9
+    assert rel(r_max, ref.history["r_max"]) < 1e-8
+
+
+def test_mixed_solve_kinds_rejected():
+    say("mixed solve kinds")
+    s, g = sc.swap_circle(4, seed=1)
+    pd = mato.Plan(4, 20, 11, 3.0, 0.4, 0.8, 1.0, "fp32")
+    ps = mato.Plan(4, 20, 11, 3.0, 0.4, 0.8, 1.0, "fp32", solve="structured")
+    with pytest.raises(mato.MatoError) as e:
+        mato.Batch([pd, ps], [s, s], [g, g])
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
+    b = mato.Batch([pd], [s], [g])
+    with pytest.raises(mato.MatoError) as e:
+        b.set_rho_schedule([[pd], [ps]], [0, 10])
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
