@@ -82,3 +82,29 @@ def poisson_arrivals(rate, count, seed=0):
     """Arrival times (s) of a Poisson process: cumulative exponential gaps of mean 1/rate."""
     rng = _rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def obstacle_box(n, n_obs, r_range=(0.2, 0.5), agent=(0.15, 0.3), clearance=1.2, min_sep=1.0, seed=0):
+    """Random-box starts and goals at the n = 64 density plus n_obs static spherical
+    obstacles (radius uniform in r_range) placed uniformly in the same box, each kept
+    away from every start and goal (scaled distance >= clearance in its own clearance
+    spheroid).  Returns starts, goals and obstacles [n_obs][x, y, z, l_xy, l_z] where
+    (l_xy, l_z) = agent semi-axes + obstacle radius."""
+    starts, goals = random_density_box(n, min_sep=min_sep, seed=seed)
+    box = np.asarray(density_box(n))
+    rng = _rng(seed + 7919)
+    pts = np.concatenate([starts, goals])
+    obs = []
+    tries = 0
+    while len(obs) < n_obs:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place %d obstacles" % n_obs)
+        r = rng.uniform(*r_range)
+        c = rng.uniform(0.0, 1.0, 3) * box
+        lxy, lz = agent[0] + r, agent[1] + r
+        d = pts - c
+        s2 = (d[:, 0] ** 2 + d[:, 1] ** 2) / lxy ** 2 + d[:, 2] ** 2 / lz ** 2
+        if np.all(s2 >= clearance ** 2):
+            obs.append([c[0], c[1], c[2], lxy, lz])
+    return starts, goals, np.asarray(obs, dtype=np.float64).reshape(-1, 5)
