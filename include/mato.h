@@ -24,7 +24,14 @@
  *   - Agents are indexed 0..n-1; pair p = (i, j), i < j, is numbered in the row
  *     order of A_fc, eq. (A_f): p(i, j) = i n - i (i + 1) / 2 + (j - i - 1).
  *   - Coefficient arrays are [agent][axis][coef] (axis order x, y, z); pairwise
- *     arrays (multipliers, d e) are [pair][time][axis].
+ *     arrays (multipliers, d e) are [row][time][axis], where the collision rows are
+ *     the pairs p(i, j) followed, with static obstacles, by row
+ *     n(n-1)/2 + i n_obs + o for agent i and obstacle o.
+ *   - Static obstacles (Sec. IV-A: circumscribing spheres) are given per problem as
+ *     [x, y, z, l_xy, l_z]: the centre and the semi-axes of the agent-obstacle
+ *     clearance spheroid (agent size plus obstacle radius).  They add one row per
+ *     agent and obstacle to A_fc, of the same form as an agent pair with the
+ *     obstacle's position fixed.
  */
 #ifndef MATO_H
 #define MATO_H
@@ -50,6 +57,7 @@ typedef int32_t mato_status;
 #define MATO_MAX_AGENTS 160          /* largest n: the pairwise stage keeps one instant of all
                                         n(n-1)/2 pairs in LDS                                  */
 #define MATO_MAX_STAGES 16           /* largest number of stages of a rho schedule             */
+#define MATO_MAX_OBSTACLES 1024      /* largest number of static obstacles per problem         */
 
 /* Trajectory basis of eq. (param): Bernstein polynomials of degree n_coef-1 over
  * [0, t_final] seconds, sampled at T uniformly spaced instants including both ends. */
@@ -118,14 +126,27 @@ mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis,
                                   const double* rhos, int32_t count, int32_t precision,
                                   void* hip_stream, mato_plan* out);
 
-/* As mato_plan_create_many, with the solve kind (mato_solve_kind).  A structured plan
- * takes MATO_FP32 (pairwise stage in FP32) or MATO_FP64; BF16_REFINED is INVALID_ARG. */
-mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
-                                const double* rhos, int32_t count, int32_t precision, int32_t solve,
+/* Everything a plan depends on (K depends on the number of obstacles, not on where they are). */
+typedef struct {
+    int32_t    n;          /* agents, 2..MATO_MAX_AGENTS                                  */
+    int32_t    n_obs;      /* static obstacles per problem, 0..MATO_MAX_OBSTACLES          */
+    int32_t    T;          /* instants, >= basis.n_coef                                    */
+    mato_basis basis;
+    double     a, b;       /* l_xy, l_z of the agent-pair clearance spheroid              */
+    int32_t    precision;  /* mato_precision                                               */
+    int32_t    solve;      /* mato_solve_kind                                              */
+} mato_plan_desc;
+
+/* General plan creation: `count` plans described by *desc with the penalties
+ * rhos[0..count), inverted in the same launches.  With obstacles K gains
+ * rho n_obs P^T P on every agent's diagonal block.  A structured plan takes MATO_FP32
+ * (pairwise stage in FP32) or MATO_FP64; BF16_REFINED is INVALID_ARG.  Errors as
+ * mato_plan_create; on error no plan is returned. */
+mato_status mato_plan_create_ex(const mato_plan_desc* desc, const double* rhos, int32_t count,
                                 void* hip_stream, mato_plan* out);
 
-/* The plan's mato_solve_kind. */
-mato_status mato_plan_solve_kind(mato_plan plan, int32_t* solve);
+/* The description a plan was created with, and its rho. */
+mato_status mato_plan_describe(mato_plan plan, mato_plan_desc* desc, double* rho);
 
 /* Sizes and diagnostics: n, T, n_coef, precision; cond = ||K||_1 ||K^{-1}||_1 (FP64)
  * (structured plans: the larger of the two per-agent estimates). */
@@ -150,6 +171,13 @@ mato_status mato_plan_inverse(mato_plan plan, double* kinv);
 mato_status mato_batch_create(int32_t count, const mato_plan* plans,
                               const double* starts, const double* goals,
                               void* hip_stream, mato_batch* out);
+
+/* As mato_batch_create, for plans with static obstacles: obstacles holds
+ * [problem][obstacle][x, y, z, l_xy, l_z], plans[q]->n_obs entries for problem q, problems
+ * in order (NULL when no plan has obstacles).  l_xy, l_z must be finite and > 0. */
+mato_status mato_batch_create_ex(int32_t count, const mato_plan* plans,
+                                 const double* starts, const double* goals, const double* obstacles,
+                                 void* hip_stream, mato_batch* out);
 void        mato_batch_destroy(mato_batch batch);
 
 /* Enqueue k iterations of Algorithm 1 for every problem not yet converged
@@ -181,7 +209,7 @@ mato_status mato_batch_residuals(mato_batch batch, int32_t q, double* r_max, dou
  * (c, lambda, d e): multipliers and the projected points of eq. (b_f)
  * (b_fc = d e - lambda / rho).  c is double [n][3][n_coef]; lambda, proj, d and X
  * are in the batch's scalar (float for MATO_FP32 / MATO_BF16_REFINED, double for
- * MATO_FP64): lambda and proj [n_pairs][T][3], d [n_pairs][T], X (positions P c of
+ * MATO_FP64): lambda and proj [n_rows][T][3], d [n_rows][T] (n_rows = n(n-1)/2 + n n_obs), X (positions P c of
  * the current c) [n][3][T].  get_state's `proj` and `d` need mato_batch_debug(batch, 1)
  * before the iteration that produced them; any output pointer may be NULL.
  * set_state rebuilds the linear term from (lambda, proj); c, if given, replaces the

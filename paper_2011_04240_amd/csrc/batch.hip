@@ -11,7 +11,8 @@ using BatchImpl = Engine<S>;
 // ----------------------------------------------------------- creation ---
 template <typename S>
 static mato_status batch_create(int count, const mato_plan* plans, const double* starts,
-                                const double* goals, hipStream_t st, BatchImpl<S>** out) {
+                                const double* goals, const double* obstacles, hipStream_t st,
+                                BatchImpl<S>** out) {
     auto* B = new BatchImpl<S>();
     B->precision = plans[0]->precision;
     B->solve = plans[0]->solve;
@@ -20,19 +21,25 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
     if (B->solve == MATO_SOLVE_STRUCTURED) B->refine = 0;     // the structured step is FP64 throughout
     B->stream = st;
     auto fail = [&](mato_status s) { delete B; return s; };
-    int agents = 0;
+    int agents = 0, nobs = 0;
     std::vector<size_t> offs;
     size_t total = 0;
     for (int q = 0; q < count; ++q) {
         offs.push_back(total);
         total += BatchImpl<S>::slot_bytes(plans[q]);
         agents += plans[q]->n;
+        nobs += plans[q]->n_obs;
     }
-    std::vector<double> hs((size_t)agents * 3), hg((size_t)agents * 3);
+    if (nobs > 0 && !obstacles) {
+        set_error("the plans have %d obstacles in total but none were given", nobs);
+        return fail(MATO_ERR_INVALID_ARG);
+    }
+    std::vector<double> hs((size_t)agents * 3), hg((size_t)agents * 3), ho((size_t)nobs * 5);
     if (hipMemcpy(hs.data(), starts, sizeof(double) * hs.size(), hipMemcpyDefault) != hipSuccess ||
-        hipMemcpy(hg.data(), goals, sizeof(double) * hg.size(), hipMemcpyDefault) != hipSuccess) {
+        hipMemcpy(hg.data(), goals, sizeof(double) * hg.size(), hipMemcpyDefault) != hipSuccess ||
+        (nobs > 0 && hipMemcpy(ho.data(), obstacles, sizeof(double) * ho.size(), hipMemcpyDefault) != hipSuccess)) {
         (void)hipGetLastError();
-        set_error("cannot read starts/goals");
+        set_error("cannot read starts/goals/obstacles");
         return fail(MATO_ERR_INVALID_ARG);
     }
     mato_status s;
@@ -47,11 +54,13 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
         set_error("arena clear failed");
         return fail(MATO_ERR_HIP);
     }
-    int a0 = 0;
+    int a0 = 0, o0 = 0;
     for (int q = 0; q < count; ++q) {
-        if ((s = B->attach(q, plans[q], &hs[(size_t)a0 * 3], &hg[(size_t)a0 * 3], B->arena + offs[q])) != MATO_OK)
+        if ((s = B->attach(q, plans[q], &hs[(size_t)a0 * 3], &hg[(size_t)a0 * 3], B->arena + offs[q],
+                           plans[q]->n_obs ? &ho[(size_t)o0 * 5] : nullptr)) != MATO_OK)
             return fail(s);
         a0 += plans[q]->n;
+        o0 += plans[q]->n_obs;
     }
     if ((s = B->enqueue_init_all()) != MATO_OK) return fail(s);
     if (hipStreamSynchronize(st) != hipSuccess) {
@@ -88,6 +97,12 @@ using namespace mato;
 // ---------------------------------------------------------------- C ABI ---
 extern "C" mato_status mato_batch_create(int32_t count, const mato_plan* plans, const double* starts,
                                          const double* goals, void* hip_stream, mato_batch* out) {
+    return mato_batch_create_ex(count, plans, starts, goals, nullptr, hip_stream, out);
+}
+
+extern "C" mato_status mato_batch_create_ex(int32_t count, const mato_plan* plans, const double* starts,
+                                            const double* goals, const double* obstacles, void* hip_stream,
+                                            mato_batch* out) {
     if (!out || !plans || !starts || !goals || count < 1) { set_error("invalid arguments"); return MATO_ERR_INVALID_ARG; }
     *out = nullptr;
     for (int q = 0; q < count; ++q)
@@ -100,11 +115,11 @@ extern "C" mato_status mato_batch_create(int32_t count, const mato_plan* plans, 
     mato_status s;
     if (b->precision == MATO_FP64) {
         BatchImpl<double>* B = nullptr;
-        s = batch_create<double>(count, plans, starts, goals, (hipStream_t)hip_stream, &B);
+        s = batch_create<double>(count, plans, starts, goals, obstacles, (hipStream_t)hip_stream, &B);
         b->impl = B;
     } else {
         BatchImpl<float>* B = nullptr;
-        s = batch_create<float>(count, plans, starts, goals, (hipStream_t)hip_stream, &B);
+        s = batch_create<float>(count, plans, starts, goals, obstacles, (hipStream_t)hip_stream, &B);
         b->impl = B;
     }
     if (s != MATO_OK) { delete b; return s; }
@@ -340,7 +355,7 @@ extern "C" mato_status mato_batch_set_rho_schedule(mato_batch b, int32_t stages,
                 const mato_plan p = plans[(size_t)j * cnt + q];
                 if (!p || p->n != P.plan->n || p->T != P.plan->T || p->nv != P.plan->nv ||
                     p->t_final != P.plan->t_final || p->precision != P.plan->precision || p->a != P.plan->a ||
-                    p->b != P.plan->b || p->solve != P.plan->solve) {
+                    p->b != P.plan->b || p->solve != P.plan->solve || p->n_obs != P.plan->n_obs) {
                     set_error("stage %d plan of problem %d does not match its sizes, basis, precision or solve kind",
                               j, q);
                     return MATO_ERR_INVALID_ARG;

@@ -20,6 +20,7 @@ constexpr int kMaxCoef = 16;
 constexpr int kHistCap = 4096;  // per-problem iteration history kept on the device
 constexpr int kMaxRefine = 4;
 constexpr int kMaxStages = MATO_MAX_STAGES;
+constexpr int kObs = 8;         // obstacle table entry: x, y, z, 1/l_xy^2, 1/l_z^2, l_z, 0, 0 (scalar S)
 constexpr int kCtrl = 8;        // control words per problem:
                                 // [0] iterations, [1] stopped, [2] non-finite, [3] active, [4] converged
 
@@ -57,7 +58,8 @@ __host__ __device__ inline int row_offset(int i, int n) { return i * n - i * (i 
 // double); coefficients, linear term, residuals and the boundary data are FP64.
 template <typename S>
 struct ProblemDesc {
-    int n, np, T, nv;           // agents, pairs, instants, coefficients per axis
+    int n, np, T, nv;           // agents, collision rows (pairs, then agent-obstacle pairs), instants, coefficients
+    int n_obs;                  // static obstacles
     int ldq;                    // stride of one axis of q / r: >= 17n, padded
     int ldc;                    // stride of one axis of c: >= 11n
     int nslab;                  // pairwise work items of this problem (residual partials)
@@ -71,7 +73,8 @@ struct ProblemDesc {
     const double* PtP;          // [nv][nv]
     const double* PddtPdd;      // [nv][nv]
     const double* A;            // [6][nv] boundary rows
-    const unsigned* pairs;      // [np] pair p -> i | j << 16
+    const unsigned* pairs;      // [np] row p -> i | j << 16 (j >= n: obstacle j - n)
+    const S* obs;               // [n_obs][kObs] obstacle table
     const double* smat;         // structured solve operands of the plan (nullptr: dense inverse)
     S* lam;                     // [T][3][np] multipliers
     S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
@@ -129,6 +132,7 @@ enum PairMode { kModeIter = 0, kModeInit = 1, kModeSetState = 2 };
 // ------------------------------------------------------------------ handles ---
 struct mato_plan_s {
     int n, T, nv, nb, precision, device;
+    int n_obs = 0;
     double t_final, a, b, rho, cond;
     hipStream_t stream;
     std::vector<double> P, Pd, Pdd, PtP, PddtPdd, A, K0inv_c;   // host FP64
@@ -142,7 +146,7 @@ struct mato_plan_s {
     int solve = MATO_SOLVE_DENSE;
     std::vector<double> Ks0, Ksn;  // structured solve: inverses of K_0 and K_{rho n}, (nv+6)^2 FP64
     double* dS = nullptr;        // structured solve: [nv][nv] M1, [nv][nv] M2, [nv][6] E0, [nv][6] En
-    unsigned* dPairs = nullptr;  // [n(n-1)/2] pair p -> i | j << 16 in the row order of A_fc
+    unsigned* dPairs = nullptr;  // [n(n-1)/2 + n n_obs] row p -> i | j << 16 in the row order of A_fc
     void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 hi or fp64
     void* dAlo = nullptr;        // bf16 lo part
     int ldk = 0;                 // padded row stride of the GEMM operand

@@ -78,6 +78,8 @@ struct Engine {
     struct Prob {
         mato_plan plan = nullptr;
         int n = 0, np = 0, T = 0, nv = 0, ldq = 0, ldc = 0;
+        int n_obs = 0;                       // static obstacles (np counts their rows)
+        size_t o_obs = 0;
         size_t o_lam = 0, o_ssum = 0, o_X = 0, o_misc = 0, o_c = 0, o_ceq = 0, o_q = 0, o_r = 0, o_qf = 0,
                o_rf = 0, o_part = 0, o_hist = 0, bytes = 0;
         char* base = nullptr;        // device block of this slot
@@ -92,6 +94,7 @@ struct Engine {
         int stage = 0;
         int iters_host = 0;                  // iterations enqueued since attach
         std::vector<double> starts, goals;   // [n][3]
+        std::vector<double> obstacles;       // [n_obs][5]: x, y, z, l_xy, l_z
     };
 
     int precision = MATO_FP32;
@@ -198,13 +201,15 @@ struct Engine {
         P.o_rf = off;   off += al(sizeof(float) * 3 * (size_t)P.ldq);
         P.o_part = off; off += al(sizeof(double) * 4 * (size_t)P.T);   // at most T slabs
         P.o_hist = off; off += al(sizeof(double) * 3 * kHistCap);
+        P.o_obs = off;  off += al(sizeof(S) * kObs * (size_t)std::max(P.n_obs, 1));
         P.bytes = off;
     }
 
     static void describe(Prob& P, mato_plan plan) {
         P.plan = plan;
         P.n = plan->n;
-        P.np = P.n * (P.n - 1) / 2;
+        P.n_obs = plan->n_obs;
+        P.np = P.n * (P.n - 1) / 2 + P.n * P.n_obs;
         P.T = plan->T;
         P.nv = plan->nv;
         P.ldq = round_up(P.n * (P.nv + kNb), 32);   // >= the operand stride ldk = round_up(11n, 32)
@@ -243,6 +248,8 @@ struct Engine {
         const mato_plan pl = P.plan;
         char* b = P.base;
         D.n = P.n; D.np = P.np; D.T = P.T; D.nv = P.nv; D.ldq = P.ldq; D.ldc = P.ldc;
+        D.n_obs = P.n_obs;
+        D.obs = (const S*)(b + P.o_obs);
         D.nslab = P.nslab; D.hist_cap = kHistCap;
         D.a = pl->a; D.b = pl->b; D.rho = pl->rho;
         D.ia2 = (S)(1.0 / (pl->a * pl->a));
@@ -296,10 +303,11 @@ struct Engine {
         Prob& P = probs[q];
         const int cap = device_lds_limit() - 1024;   // room for the kernel's static reduction buffer
         const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S);
+        const size_t fixed = (size_t)kObs * P.n_obs * sizeof(S);
         int tc = std::max(1, items_per_wg / std::max(1, P.np));
         tc = std::min(tc, P.T);
-        while (tc > 1 && per_t * tc > (size_t)cap) --tc;
-        *maxlds = std::max(*maxlds, per_t * tc);
+        while (tc > 1 && per_t * tc + fixed > (size_t)cap) --tc;
+        *maxlds = std::max(*maxlds, per_t * tc + fixed);
         P.nslab = (P.T + tc - 1) / tc;
         for (int s = 0; s < P.nslab; ++s) {
             WorkItem w;
@@ -312,10 +320,10 @@ struct Engine {
     }
 
     mato_status check_lds(const Prob& P) const {
-        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S);
+        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S) + (size_t)kObs * P.n_obs * sizeof(S);
         if (per_t > (size_t)(device_lds_limit() - 1024)) {
-            set_error("n = %d needs %zu bytes of LDS per instant, device allows %d", P.n, per_t,
-                      device_lds_limit() - 1024);
+            set_error("n = %d, n_obs = %d needs %zu bytes of LDS per instant, device allows %d", P.n, P.n_obs,
+                      per_t, device_lds_limit() - 1024);
             return MATO_ERR_UNSUPPORTED;
         }
         return MATO_OK;
@@ -395,7 +403,8 @@ struct Engine {
     // --------------------------------------------------------- slots ---
     // Binds slot q to a problem: device block (arena part or own, reused when large
     // enough), boundary data, control words, descriptor.  Does not initialise.
-    mato_status attach(int q, mato_plan plan, const double* starts, const double* goals, char* arena_part) {
+    mato_status attach(int q, mato_plan plan, const double* starts, const double* goals, char* arena_part,
+                       const double* obstacles = nullptr) {
         Prob& P = probs[q];
         describe(P, plan);
         MATO_TRY(check_lds(P));
@@ -421,6 +430,20 @@ struct Engine {
         }
         P.starts.assign(starts, starts + 3 * (size_t)P.n);
         P.goals.assign(goals, goals + 3 * (size_t)P.n);
+        P.obstacles.assign((size_t)5 * P.n_obs, 0.0);
+        if (P.n_obs > 0) {
+            if (!obstacles) {
+                set_error("the plan has %d obstacles but none were given", P.n_obs);
+                return MATO_ERR_INVALID_ARG;
+            }
+            P.obstacles.assign(obstacles, obstacles + (size_t)5 * P.n_obs);
+            for (int o = 0; o < P.n_obs; ++o) {
+                const double* ob = &P.obstacles[(size_t)5 * o];
+                for (int k = 0; k < 5; ++k)
+                    if (!std::isfinite(ob[k])) { set_error("non-finite obstacle"); return MATO_ERR_NONFINITE; }
+                if (!(ob[3] > 0) || !(ob[4] > 0)) { set_error("obstacle semi-axes must be > 0"); return MATO_ERR_INVALID_ARG; }
+            }
+        }
         P.stage = 0;
         P.iters_host = 0;
         for (size_t k = 0; k < P.starts.size(); ++k)
@@ -461,9 +484,20 @@ struct Engine {
         P.plan = nullptr;
     }
 
-    // Boundary rows of q: [start, 0, 0, goal, 0, 0] per agent and axis, FP64 and FP32.
+    // Boundary rows of q: [start, 0, 0, goal, 0, 0] per agent and axis, FP64 and FP32;
+    // and the obstacle table.
     mato_status upload_beq(int q) {
         const Prob& P = probs[q];
+        std::vector<S> ho((size_t)kObs * P.n_obs, S(0));      // kept until the synchronisation below
+        if (P.n_obs > 0) {
+            for (int o = 0; o < P.n_obs; ++o) {
+                const double* ob = &P.obstacles[(size_t)5 * o];
+                S* e = &ho[(size_t)kObs * o];
+                e[0] = (S)ob[0]; e[1] = (S)ob[1]; e[2] = (S)ob[2];
+                e[3] = (S)(1.0 / (ob[3] * ob[3])); e[4] = (S)(1.0 / (ob[4] * ob[4])); e[5] = (S)ob[4];
+            }
+            MATO_HIP(hipMemcpyAsync(P.base + P.o_obs, ho.data(), sizeof(S) * ho.size(), hipMemcpyHostToDevice, stream));
+        }
         std::vector<double> hq((size_t)3 * P.ldq, 0.0);
         for (int a = 0; a < 3; ++a)
             for (int i = 0; i < P.n; ++i) {

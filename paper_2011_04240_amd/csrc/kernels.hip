@@ -13,7 +13,7 @@
 //   qbuild_kernel    g = rho A_fc^T b_fc = rho P^T S_i (FP64), plus the iteration's
 //                    residual record and the convergence test.
 //   residual_kernel  FP64 refinement residual g - H c of eq. (kkt_step_x), with
-//                    H c = (I (x) Pdd^T Pdd) c + rho ((n I - 1 1^T) (x) P^T P) c.
+//                    H c = (I (x) Pdd^T Pdd) c + rho (((n + n_obs) I - 1 1^T) (x) P^T P) c.
 //   ceq_kernel       c_eq = K12^{-1} b_eq, the boundary part of the inverse product.
 //   init_kernel      boundary-only minimum-acceleration coefficients (initialisation).
 //
@@ -88,8 +88,9 @@ struct Recip<double> {
 };
 
 // One workgroup per work item: instants [t0, t0 + tc) of one problem, all pairs.
-// LDS: X [tc][3][n] (copied from the positions of the current coefficients) then
-// b_fc [tc][3][n_pairs] (scalar S).
+// LDS: X [tc][3][n] (copied from the positions of the current coefficients), then
+// b_fc [tc][3][n_rows] (scalar S), then the obstacle table.  Rows after the agent
+// pairs pair an agent with a static obstacle (fixed centre, own semi-axes).
 // Threads form `tg` instant groups of `pw` pair lanes (pw = the smallest power of two
 // >= n_pairs, between 64 and BLOCK).  A lane owns U pairs of a chunk and walks its
 // group's instants; the multipliers of the next (chunk, instant) are loaded while the
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     gptr<const int> ctrl = glob((const int*)Dp->ctrl);
     if (!ctrl[3]) return;                          // inactive slot
     if (MODE == kModeIter && ctrl[1]) return;      // converged
-    const int n = Dp->n, np = Dp->np;
+    const int n = Dp->n, np = Dp->np, n_obs = Dp->n_obs;
     const int t0 = it.t0, tc = it.tc;
     gptr<const S> Xm = glob((const S*)Dp->X);
     gptr<const unsigned> pairs = glob(Dp->pairs);
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S* Xs = reinterpret_cast<S*>(smem_raw);
     S* Bs = Xs + tc * 3 * n;
+    S* Os = Bs + (size_t)tc * 3 * np;                // obstacle table [n_obs][kObs]
     const int tid = threadIdx.x;
 
     int pw = 64;
@@ -161,6 +163,10 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     };
     if (nit > 0) fetch(0);
 
+    if (n_obs > 0) {
+        gptr<const S> og = glob(Dp->obs);
+        for (int idx = tid; idx < n_obs * kObs; idx += BLOCK) Os[idx] = og[idx];
+    }
     if (MODE != kModeSetState) {
         // positions of the block's instants: one contiguous slab of X [t][3][n]
         const int nX = tc * 3 * n;
@@ -197,12 +203,27 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
                 continue;
             }
             const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
-            const S dx = X[i] - X[j];
-            const S dy = X[n + i] - X[n + j];
-            const S dz = X[2 * n + i] - X[2 * n + j];
+            // partner: agent j, or (rows after the pairs) static obstacle j - n with its own axes
+            S xj, yj, zj, ia2p = ia2, ib2p = ib2, lzp = lzl;
+            if (j < n) {
+                xj = X[j];
+                yj = X[n + j];
+                zj = X[2 * n + j];
+            } else {
+                const S* ob = Os + (j - n) * kObs;
+                xj = ob[0];
+                yj = ob[1];
+                zj = ob[2];
+                ia2p = ob[3];
+                ib2p = ob[4];
+                lzp = ob[5];
+            }
+            const S dx = X[i] - xj;
+            const S dy = X[n + i] - yj;
+            const S dz = X[2 * n + i] - zj;
             S px, py, pz, dd;
             if (!shifted) {
-                const S q2 = (dx * dx + dy * dy) * ia2 + dz * dz * ib2;   // s^2
+                const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2
                 if (q2 > 0) {
                     const S D2 = dx * dx + dy * dy + dz * dz;
                     const S rs = Recip<S>::rsq(q2);                     // 1 / s
@@ -213,15 +234,15 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
                     pz = w * dz;
                     dd = w * (q2 * rs);                                 // d = w s
                 } else {                                                // delta = 0: e = (0, 0, l_z)
-                    dd = fmax(S(1), lzm * irho / lzl);
+                    dd = fmax(S(1), lzm * irho / lzp);
                     px = 0;
                     py = 0;
-                    pz = dd * lzl;
+                    pz = dd * lzp;
                 }
             } else {
                 // variant: project v = delta + lambda/rho; then d = max(1, s_v), d e = max(1/s_v, 1) v
                 const S vx = dx + lx * irho, vy = dy + ly * irho, vz = dz + lzm * irho;
-                const S q2 = (vx * vx + vy * vy) * ia2 + vz * vz * ib2;
+                const S q2 = (vx * vx + vy * vy) * ia2p + vz * vz * ib2p;
                 if (q2 > 0) {
                     const S rs = Recip<S>::rsq(q2);
                     const S w = fmax(rs, S(1));
@@ -233,7 +254,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
                     dd = S(1);
                     px = 0;
                     py = 0;
-                    pz = lzl;
+                    pz = lzp;
                 }
             }
             const S fx = dx - px, fy = dy - py, fz = dz - pz;
@@ -263,7 +284,8 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     }
     __syncthreads();
 
-    // S_i(t) = sum_{j<i} (-b_ji) + sum_{j>i} b_ij, j ascending (fixed order)
+    // S_i(t) = sum_{j<i} (-b_ji) + sum_{j>i} b_ij, j ascending (fixed order), then
+    // sum_o (x_o + b_io) over static obstacles, o ascending
     const int n3 = 3 * n;
     const int nS = tc * n3;
     for (int o = tid; o < nS; o += BLOCK) {
@@ -281,6 +303,10 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         const S* row = Bt + row_offset(i, n) - i - 1;
 #pragma unroll 8
         for (int j = i + 1; j < n; ++j) acc += row[j];
+        if (n_obs > 0) {                    // agent-obstacle rows: target x_o + d e - lambda / rho
+            const S* ro = Bt + n * (n - 1) / 2 + (size_t)i * n_obs;
+            for (int o = 0; o < n_obs; ++o) acc += Os[o * kObs + a] + ro[o];
+        }
         ssum[((size_t)(t0 + tl) * 3 + a) * n + i] = acc;
     }
 
@@ -530,7 +556,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const ProblemDesc<S>* __r
         csum[threadIdx.x] = s;
     }
     __syncthreads();
-    const double nr = (double)n * rho;
+    const double nr = (double)(n + Dp->n_obs) * rho;        // diagonal weight: agent pairs and obstacles
     for (int o = threadIdx.x; o < n * nv; o += blockDim.x) {
         const int i = o / nv, k = o - i * nv;
         const double* ci = cs + i * nv;

@@ -71,7 +71,7 @@ static void gram(const std::vector<double>& X, int T, int nv, std::vector<double
 //   H_(i,k),(j,l) = delta_ij Pdd^T Pdd[k][l] + rho (n delta_ij - 1) P^T P[k][l]
 // (the collision Gram A_fc^T A_fc = (n I - 1 1^T) (x) P^T P), A_eq = I (x) A.
 // Written into the left half of the augmented matrix W = [K | I].
-__global__ void assemble_kkt(double* __restrict__ W, int n, int nv, int nb, double rho,
+__global__ void assemble_kkt(double* __restrict__ W, int n, int n_obs, int nv, int nb, double rho,
                              const double* __restrict__ PtP, const double* __restrict__ PddtPdd,
                              const double* __restrict__ A) {
     const int N = n * (nv + nb);
@@ -85,7 +85,7 @@ __global__ void assemble_kkt(double* __restrict__ W, int n, int nv, int nb, doub
             v = (c - N == r) ? 1.0 : 0.0;
         } else if (r < nc && c < nc) {
             const int i = r / nv, k = r % nv, j = c / nv, l = c % nv;
-            v = rho * ((i == j ? n : 0) - 1) * PtP[k * nv + l];
+            v = rho * ((i == j ? n + n_obs : 0) - 1) * PtP[k * nv + l];
             if (i == j) v += PddtPdd[k * nv + l];
         } else if (r < nc && c >= nc) {
             const int i = r / nv, k = r % nv, j = (c - nc) / nb, b = (c - nc) % nb;
@@ -318,6 +318,8 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
     std::vector<unsigned> pairs;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) pairs.push_back((unsigned)i | ((unsigned)j << 16));
+    for (int i = 0; i < n; ++i)                  // agent-obstacle rows: partner n + o
+        for (int o = 0; o < p0->n_obs; ++o) pairs.push_back((unsigned)i | ((unsigned)(n + o) << 16));
     for (auto p : ps) {
         if (p != p0) {
             p->P = p0->P; p->Pd = p0->Pd; p->Pdd = p0->Pdd;
@@ -333,16 +335,21 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
 
     // Per-agent KKT matrices K_sigma = [[Pdd^T Pdd + sigma P^T P, A^T], [A, 0]].  K_0 is the
     // boundary-only minimum-acceleration problem (initialisation).  With the structured
-    // solve also K_{rho n} for every rho: the complete-graph Laplacian n I - 1 1^T has the
-    // eigenvalue 0 on the agent mean and n on every deviation from it, so
-    //     K^{-1} = (1 1^T / n) (x) K_0^{-1} + (I - 1 1^T / n) (x) K_{rho n}^{-1}
-    // in per-agent ordering, and c_i = K_0^{-1} [g_mean; b_mean] + K_{rho n}^{-1} [g_i - g_mean; b_i - b_mean].
+    // solve also, for every rho, the mean block K_{rho n_obs} and the deviation block
+    // K_{rho (n + n_obs)}: A_fc^T A_fc = ((n + n_obs) I - 1 1^T) (x) P^T P, whose eigenvalues
+    // are n_obs on the agent mean and n + n_obs on every deviation from it, so
+    //     K^{-1} = (1 1^T / n) (x) K_mean^{-1} + (I - 1 1^T / n) (x) K_dev^{-1}
+    // in per-agent ordering, and c_i = K_mean^{-1} [g_mean; b_mean] + K_dev^{-1} [g_i - g_mean; b_i - b_mean].
     const bool structured = p0->solve == MATO_SOLVE_STRUCTURED;
+    const int n_obs = p0->n_obs;
     {
-        const int N0 = nv + nb, m0 = structured ? cnt + 1 : 1;
+        const int N0 = nv + nb, m0 = structured ? 2 * cnt + 1 : 1;
         const size_t ms0 = (size_t)N0 * 2 * N0;
         std::vector<double> sig(m0, 0.0);
-        for (int m = 1; m < m0; ++m) sig[m] = ps[m - 1]->rho * n;
+        for (int m = 0; 2 * m + 2 < m0; ++m) {
+            sig[2 * m + 1] = ps[m]->rho * n_obs;
+            sig[2 * m + 2] = ps[m]->rho * (n + n_obs);
+        }
         double *W0 = nullptr, *inv0 = nullptr, *dsig = nullptr;
         MATO_HIP(hipMalloc(&W0, sizeof(double) * ms0 * m0));
         MATO_HIP(hipMalloc(&inv0, sizeof(double) * N0 * N0 * m0));
@@ -370,11 +377,11 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         if (structured) {
             for (int m = 0; m < cnt; ++m) {
                 mato_plan p = ps[m];
-                const double* K0i = h.data();
-                const double* Kni = h.data() + (size_t)N0 * N0 * (m + 1);
+                const double* K0i = h.data() + (size_t)N0 * N0 * (2 * m + 1);
+                const double* Kni = h.data() + (size_t)N0 * N0 * (2 * m + 2);
                 p->Ks0.assign(K0i, K0i + (size_t)N0 * N0);
                 p->Ksn.assign(Kni, Kni + (size_t)N0 * N0);
-                p->cond = std::max(conds[0], conds[m + 1]);
+                p->cond = std::max(conds[2 * m + 1], conds[2 * m + 2]);
                 std::vector<double> S((size_t)2 * nv * nv + (size_t)2 * nv * nb);
                 double* M1 = S.data();
                 double* M2 = M1 + nv * nv;
@@ -412,7 +419,7 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         MATO_HIP(hipMalloc(&ps[m]->dKinv, sizeof(double) * (size_t)N * N));
         ps[m]->bytes += sizeof(double) * (size_t)N * N;
         invs[m] = ps[m]->dKinv;
-        assemble_kkt<<<grid_for(ms, 256), 256, 0, st>>>(W + ms * m, n, nv, nb, ps[m]->rho, ps[m]->dPtP,
+        assemble_kkt<<<grid_for(ms, 256), 256, 0, st>>>(W + ms * m, n, n_obs, nv, nb, ps[m]->rho, ps[m]->dPtP,
                                                         ps[m]->dPddtPdd, ps[m]->dA);
     }
     mato_status s = gauss_jordan(W, N, cnt, invs.data(), conds.data(), st);
@@ -487,17 +494,20 @@ static mato_status check_plan_args(int32_t n, int32_t T, const mato_basis* basis
     return MATO_OK;
 }
 
-extern "C" mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
-                                           const double* rhos, int32_t count, int32_t precision, int32_t solve,
+extern "C" mato_status mato_plan_create_ex(const mato_plan_desc* d, const double* rhos, int32_t count,
                                            void* hip_stream, mato_plan* out) {
-    if (!out || !rhos || count < 1) { set_error("null argument or count < 1"); return MATO_ERR_INVALID_ARG; }
+    if (!d || !out || !rhos || count < 1) { set_error("null argument or count < 1"); return MATO_ERR_INVALID_ARG; }
     for (int m = 0; m < count; ++m) out[m] = nullptr;
-    MATO_TRY(check_plan_args(n, T, basis, a, b, precision));
-    if (solve != MATO_SOLVE_DENSE && solve != MATO_SOLVE_STRUCTURED) {
-        set_error("unknown solve kind %d", solve);
+    MATO_TRY(check_plan_args(d->n, d->T, &d->basis, d->a, d->b, d->precision));
+    if (d->n_obs < 0 || d->n_obs > MATO_MAX_OBSTACLES) {
+        set_error("n_obs = %d outside 0..%d", d->n_obs, MATO_MAX_OBSTACLES);
         return MATO_ERR_INVALID_ARG;
     }
-    if (solve == MATO_SOLVE_STRUCTURED && precision == MATO_BF16_REFINED) {
+    if (d->solve != MATO_SOLVE_DENSE && d->solve != MATO_SOLVE_STRUCTURED) {
+        set_error("unknown solve kind %d", d->solve);
+        return MATO_ERR_INVALID_ARG;
+    }
+    if (d->solve == MATO_SOLVE_STRUCTURED && d->precision == MATO_BF16_REFINED) {
         set_error("the structured solve has no BF16 product: use MATO_FP32 or MATO_FP64");
         return MATO_ERR_INVALID_ARG;
     }
@@ -511,9 +521,10 @@ extern "C" mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basi
     std::vector<mato_plan> ps;
     for (int m = 0; m < count; ++m) {
         mato_plan p = new mato_plan_s();
-        p->n = n; p->T = T; p->nv = basis->n_coef; p->nb = kNb; p->precision = precision;
-        p->t_final = basis->t_final; p->a = a; p->b = b; p->rho = rhos[m]; p->cond = 0.0;
-        p->solve = solve;
+        p->n = d->n; p->T = d->T; p->nv = d->basis.n_coef; p->nb = kNb; p->precision = d->precision;
+        p->t_final = d->basis.t_final; p->a = d->a; p->b = d->b; p->rho = rhos[m]; p->cond = 0.0;
+        p->solve = d->solve;
+        p->n_obs = d->n_obs;
         p->stream = (hipStream_t)hip_stream;
         p->device = device;
         ps.push_back(p);
@@ -530,7 +541,11 @@ extern "C" mato_status mato_plan_create_ex(int32_t n, int32_t T, const mato_basi
 extern "C" mato_status mato_plan_create_many(int32_t n, int32_t T, const mato_basis* basis, double a, double b,
                                              const double* rhos, int32_t count, int32_t precision,
                                              void* hip_stream, mato_plan* out) {
-    return mato_plan_create_ex(n, T, basis, a, b, rhos, count, precision, MATO_SOLVE_DENSE, hip_stream, out);
+    if (!basis) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    mato_plan_desc d;
+    d.n = n; d.n_obs = 0; d.T = T; d.basis = *basis; d.a = a; d.b = b; d.precision = precision;
+    d.solve = MATO_SOLVE_DENSE;
+    return mato_plan_create_ex(&d, rhos, count, hip_stream, out);
 }
 
 extern "C" mato_status mato_plan_create(int32_t n, int32_t T, const mato_basis* basis, double a,
@@ -571,7 +586,7 @@ extern "C" mato_status mato_plan_inverse(mato_plan p, double* kinv) {
             for (size_t C = 0; C < N; ++C) {
                 int j, kc;
                 split(C, &j, &kc);
-                const double e0 = p->Ks0[(size_t)kr * N0 + kc], en = p->Ksn[(size_t)kr * N0 + kc];
+                const double e0 = p->Ks0[(size_t)kr * N0 + kc], en = p->Ksn[(size_t)kr * N0 + kc];   // mean, deviation
                 h[R * N + C] = e0 / n + ((i == j ? 1.0 : 0.0) - 1.0 / n) * en;
             }
         }
@@ -583,8 +598,13 @@ extern "C" mato_status mato_plan_inverse(mato_plan p, double* kinv) {
     return MATO_OK;
 }
 
-extern "C" mato_status mato_plan_solve_kind(mato_plan p, int32_t* solve) {
-    if (!p || !solve) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
-    *solve = p->solve;
+extern "C" mato_status mato_plan_describe(mato_plan p, mato_plan_desc* d, double* rho) {
+    if (!p) { set_error("null plan"); return MATO_ERR_INVALID_ARG; }
+    if (d) {
+        d->n = p->n; d->n_obs = p->n_obs; d->T = p->T;
+        d->basis.kind = MATO_BASIS_BERNSTEIN; d->basis.n_coef = p->nv; d->basis.t_final = p->t_final;
+        d->a = p->a; d->b = p->b; d->precision = p->precision; d->solve = p->solve;
+    }
+    if (rho) *rho = p->rho;
     return MATO_OK;
 }

@@ -128,8 +128,10 @@ struct ServerOps {
                                                                        s->cfg.solve);
             if (!make_room(s, est, keep, -1)) return MATO_OK;     // not now: wait for memory
             std::vector<mato_plan> made(missing.size(), nullptr);
-            MATO_TRY(mato_plan_create_ex(n, s->cfg.T, &s->cfg.basis, s->cfg.a, s->cfg.b, rhos.data(),
-                                         (int)rhos.size(), s->cfg.precision, s->cfg.solve, s->stream, made.data()));
+            mato_plan_desc d;
+            d.n = n; d.n_obs = 0; d.T = s->cfg.T; d.basis = s->cfg.basis; d.a = s->cfg.a; d.b = s->cfg.b;
+            d.precision = s->cfg.precision; d.solve = s->cfg.solve;
+            MATO_TRY(mato_plan_create_ex(&d, rhos.data(), (int)rhos.size(), s->stream, made.data()));
             for (size_t m = 0; m < missing.size(); ++m) s->plans[n * kMaxStages + missing[m]] = made[m];
         }
         for (int j = 0; j < stages(s); ++j) out->push_back(s->plans[n * kMaxStages + j]);

@@ -26,6 +26,7 @@ MATO_ERR_NOT_FOUND = -7
 MATO_WARN_NOT_CONVERGED = 1
 MATO_MAX_AGENTS = 160
 MATO_MAX_STAGES = 16
+MATO_MAX_OBSTACLES = 1024
 
 MATO_FP64, MATO_FP32, MATO_BF16_REFINED = 0, 1, 2
 PRECISIONS = {"fp64": MATO_FP64, "fp32": MATO_FP32, "bf16": MATO_BF16_REFINED}
@@ -41,6 +42,12 @@ class MatoError(RuntimeError):
 
 class _Basis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_coef", ctypes.c_int32), ("t_final", ctypes.c_double)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_obs", ctypes.c_int32), ("T", ctypes.c_int32), ("basis", _Basis),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("solve", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -62,12 +69,12 @@ SIGNATURES = {
     "mato_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _f64, _i32, _vp, _pvp]),
     "mato_plan_destroy": (None, [_vp]),
     "mato_plan_create_many": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _pf64, _i32, _i32, _vp, _pvp]),
-    "mato_plan_create_ex": (_i32, [_i32, _i32, ctypes.POINTER(_Basis), _f64, _f64, _pf64, _i32, _i32, _i32, _vp,
-                                   _pvp]),
-    "mato_plan_solve_kind": (_i32, [_vp, _pi32]),
+    "mato_plan_create_ex": (_i32, [ctypes.POINTER(PlanDesc), _pf64, _i32, _vp, _pvp]),
+    "mato_plan_describe": (_i32, [_vp, ctypes.POINTER(PlanDesc), _pf64]),
     "mato_plan_info": (_i32, [_vp, _pi32, _pi32, _pi32, _pi32, _pf64]),
     "mato_plan_inverse": (_i32, [_vp, _vp]),
     "mato_batch_create": (_i32, [_i32, _pvp, _vp, _vp, _vp, _pvp]),
+    "mato_batch_create_ex": (_i32, [_i32, _pvp, _vp, _vp, _vp, _vp, _pvp]),
     "mato_batch_destroy": (None, [_vp]),
     "mato_batch_step": (_i32, [_vp, _i32, _f64, _i32]),
     "mato_batch_run": (_i32, [_vp, _i32, _f64, _i32]),
@@ -167,19 +174,18 @@ def mato_plan_create_many(n, T, n_coef, t_final, a, b, rhos, precision, stream=N
     return [ctypes.c_void_p(x) for x in out]
 
 
-def mato_plan_create_ex(n, T, n_coef, t_final, a, b, rhos, precision, solve, stream=None):
+def mato_plan_create_ex(desc, rhos, stream=None):
     out = (ctypes.c_void_p * len(rhos))()
     r = (ctypes.c_double * len(rhos))(*rhos)
-    basis = _Basis(0, n_coef, t_final)
-    _check(lib().mato_plan_create_ex(n, T, ctypes.byref(basis), a, b, r, len(rhos), precision, solve,
-                                     _stream_ptr(stream), out))
+    _check(lib().mato_plan_create_ex(ctypes.byref(desc), r, len(rhos), _stream_ptr(stream), out))
     return [ctypes.c_void_p(x) for x in out]
 
 
-def mato_plan_solve_kind(plan):
-    v = _i32()
-    _check(lib().mato_plan_solve_kind(plan, ctypes.byref(v)))
-    return v.value
+def mato_plan_describe(plan):
+    d = PlanDesc()
+    rho = _f64()
+    _check(lib().mato_plan_describe(plan, ctypes.byref(d), ctypes.byref(rho)))
+    return d, rho.value
 
 
 def mato_plan_destroy(plan):
@@ -203,6 +209,14 @@ def mato_batch_create(plans, starts, goals, stream=None):
     h = ctypes.c_void_p()
     _check(lib().mato_batch_create(len(plans), arr, _ptr(starts), _ptr(goals), _stream_ptr(stream),
                                    ctypes.byref(h)))
+    return h
+
+
+def mato_batch_create_ex(plans, starts, goals, obstacles, stream=None):
+    arr = (ctypes.c_void_p * len(plans))(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    h = ctypes.c_void_p()
+    _check(lib().mato_batch_create_ex(len(plans), arr, _ptr(starts), _ptr(goals), _ptr(obstacles),
+                                      _stream_ptr(stream), ctypes.byref(h)))
     return h
 
 
@@ -342,27 +356,39 @@ def mato_server_run_trace(server, arrival_s, ns, starts, goals, latency, iters, 
 
 
 # ---------------------------------------------------------------- owners ---
+def plan_desc(n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, precision="fp32", solve="dense", n_obs=0):
+    pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    sv = SOLVES[solve] if isinstance(solve, str) else int(solve)
+    return PlanDesc(n, n_obs, T, _Basis(0, n_coef, t_final), a, b, pr, sv)
+
+
 class Plan:
-    """K^{-1} of the x/y/z step for one (n, T, basis, rho); a, b are the spheroid dimensions."""
+    """K^{-1} of the x/y/z step for one (n, n_obs, T, basis, rho); a, b are the spheroid dimensions."""
 
     def __init__(self, n, T, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", stream=None,
-                 handle=None, solve="dense"):
+                 handle=None, solve="dense", n_obs=0):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.solve = SOLVES[solve] if isinstance(solve, str) else int(solve)
-        self.n, self.T, self.n_coef = n, T, n_coef
+        self.n, self.T, self.n_coef, self.n_obs = n, T, n_coef, n_obs
         self.t_final, self.a, self.b, self.rho = t_final, a, b, rho
         if handle is None:
-            handle = mato_plan_create_ex(n, T, n_coef, t_final, a, b, [rho], self.precision, self.solve, stream)[0]
+            desc = plan_desc(n, T, n_coef, t_final, a, b, self.precision, self.solve, n_obs)
+            handle = mato_plan_create_ex(desc, [rho], stream)[0]
         self.handle = handle
 
     @classmethod
     def schedule(cls, n, T, rhos, n_coef=11, t_final=10.0, a=0.3, b=0.6, precision="fp32", stream=None,
-                 solve="dense"):
+                 solve="dense", n_obs=0):
         """Plans for several rho (a rho schedule), inverted together."""
-        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        sv = SOLVES[solve] if isinstance(solve, str) else int(solve)
-        hs = mato_plan_create_ex(n, T, n_coef, t_final, a, b, list(rhos), pr, sv, stream)
-        return [cls(n, T, n_coef, t_final, a, b, r, pr, handle=h, solve=sv) for r, h in zip(rhos, hs)]
+        desc = plan_desc(n, T, n_coef, t_final, a, b, precision, solve, n_obs)
+        hs = mato_plan_create_ex(desc, list(rhos), stream)
+        return [cls(n, T, n_coef, t_final, a, b, r, desc.precision, handle=h, solve=desc.solve, n_obs=n_obs)
+                for r, h in zip(rhos, hs)]
+
+    @property
+    def n_rows(self):
+        """Collision rows: agent pairs, then agent-obstacle pairs."""
+        return self.n * (self.n - 1) // 2 + self.n * self.n_obs
 
     @property
     def scalar(self):
@@ -456,12 +482,18 @@ class Server:
 class Batch:
     """Independent problems iterated together; problem q uses plans[q]."""
 
-    def __init__(self, plans, starts_list, goals_list, stream=None):
+    def __init__(self, plans, starts_list, goals_list, stream=None, obstacles_list=None):
+        """obstacles_list[q]: problem q's obstacles [n_obs][x, y, z, l_xy, l_z] (plans with n_obs > 0)."""
         self.plans = list(plans)
         self.ns = [p.n for p in self.plans]
         starts = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64).reshape(-1, 3) for s in starts_list]))
         goals = np.ascontiguousarray(np.concatenate([np.asarray(g, np.float64).reshape(-1, 3) for g in goals_list]))
-        self.handle = mato_batch_create([p.handle for p in self.plans], starts, goals, stream)
+        obs = None
+        if obstacles_list is not None:
+            rows = [np.asarray(o, np.float64).reshape(-1, 5) for o in obstacles_list]
+            if sum(len(r) for r in rows):
+                obs = np.ascontiguousarray(np.concatenate(rows))
+        self.handle = mato_batch_create_ex([p.handle for p in self.plans], starts, goals, obs, stream)
 
     def __len__(self):
         return len(self.plans)
@@ -496,7 +528,7 @@ class Batch:
 
     def get_state(self, q, proj=False, d=False, X=False):
         p = self.plans[q]
-        np_, S = p.n * (p.n - 1) // 2, p.scalar
+        np_, S = p.n_rows, p.scalar
         c = np.empty((p.n, 3, p.n_coef), np.float64)
         lam = np.empty((np_, p.T, 3), S)
         pj = np.empty((np_, p.T, 3), S) if proj else None

@@ -70,7 +70,14 @@ def test_null_handles_are_rejected():
 ])
 def test_solve_kind_validation(precision, solve):
     with pytest.raises(mato.MatoError) as e:
-        mato.mato_plan_create_ex(4, 50, 11, 5.0, 0.4, 0.8, [1.0], precision, solve)
+        mato.mato_plan_create_ex(mato.plan_desc(4, 50, 11, 5.0, 0.4, 0.8, precision, solve), [1.0])
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n_obs", [-1, mato.MATO_MAX_OBSTACLES + 1])
+def test_obstacle_count_validation(n_obs):
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_plan_create_ex(mato.plan_desc(4, 50, n_obs=n_obs), [1.0])
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
 
 

@@ -216,7 +216,8 @@ def test_structured_inverse_matches_oracle(name):
     c = CASES[name]
     say("structured inverse", name)
     gp = _gpu_plan(c, "fp64", "structured")
-    assert mato.mato_plan_solve_kind(gp.handle) == mato.MATO_SOLVE_STRUCTURED
+    desc, rho = mato.mato_plan_describe(gp.handle)
+    assert desc.solve == mato.MATO_SOLVE_STRUCTURED and (desc.n, desc.n_obs, rho) == (c["n"], 0, 1.0)
     assert rel(gp.inverse(), _oracle_plan(c).Kinv) < 1e-10
 
 
