@@ -9,10 +9,11 @@ Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step),
 the roofline of the pairwise kernel (24 algorithmic bytes per pair-instant:
 the FP32 multipliers read and written), timed with HIP events on the batch's
 stream, and the FP64 oracle timed on the host on a bounded sample.  Also in the
-line: served p50/p99 solve latency of a short Poisson trace through the
-continuous-batching server (agent counts 4..128), and uneven-size batching
-(256 problems, n in {8, 12, ..., 48}) against the same problems solved one at a
-time.  `--serve-sweep` replaces all of this by the latency sweep over arrival rates.
+line: the same step with the structured x/y/z solve, served p50/p99 solve latency
+of a short Poisson trace through the continuous-batching server (agent counts
+4..128), uneven-size batching (256 problems, n in {8, 12, ..., 48}) against the
+same problems solved one at a time, and the iteration time against the number of
+static obstacles (16 agents).  `--serve-sweep` replaces all of this by the latency sweep over arrival rates.
 """
 import argparse
 import hashlib
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--T", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--solve", default="dense", choices=["dense", "structured"],
+                    help="x/y/z step of the timed iteration (the structured variant is also timed beside it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -47,6 +50,7 @@ def parse():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=100.0)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-sweep", action="store_true",
@@ -61,10 +65,16 @@ def parse():
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "common.h"):
-        with open(os.path.join(ROOT, "paper_2011_04240_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    """Hash of the pairwise kernel's source (its block of kernels.hip, from its leading
+    comment to the next kernel's) and of the shared declarations it uses."""
+    csrc = os.path.join(ROOT, "paper_2011_04240_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        text = fh.read()
+    a = text.index("// One workgroup per work item:")
+    b = text.index("// One workgroup per problem: X = P c", a)
+    h = hashlib.sha256(text[a:b].encode())
+    with open(os.path.join(csrc, "common.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -161,6 +171,33 @@ def structured_step(n, T, B, starts, goals, args):
     return {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": upd / wall, "precision": "fp32"}
 
 
+def obstacle_scaling(n=16, counts=(0, 8, 16, 32, 64, 128), batch=256, iters=30):
+    """Iteration time against the number of static obstacles (16 agents, T = 100): one
+    problem alone and `batch` problems per launch; structured solve, FP32, graphs."""
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+    out = []
+    for k in counts:
+        scen = [sc.obstacle_box(n, k, seed=30000 + q) for q in range(batch)]
+        plan = mato.Plan(n, 100, 11, 10.0, 0.3, 0.6, 1.0, "fp32", solve="structured", n_obs=k)
+        row = {"n_obs": k, "rows": n * (n - 1) // 2 + n * k}
+        for label, m in (("single", 1), ("batch", batch)):
+            b = mato.Batch([plan] * m, [x[0] for x in scen[:m]], [x[1] for x in scen[:m]],
+                           obstacles_list=[x[2] for x in scen[:m]])
+            b.step(3)
+            b.sync()
+            t0 = time.perf_counter()
+            b.step(iters)
+            b.sync()
+            dt = (time.perf_counter() - t0) / iters
+            b.close()
+            row[label + "_ms_per_iter"] = dt * 1e3
+            row[label + "_row_updates_per_s"] = row["rows"] * 100 * m / dt
+        out.append(row)
+    return {"agents": n, "T": 100, "problems_per_launch": batch, "solve": "structured", "precision": "fp32",
+            "points": out}
+
+
 def mixed_batching(count=256, iters=30, seed=0):
     """Uneven sizes in one launch per stage (graph-replayed, autotuned tiles) against the
     plain per-problem method (each problem alone, separate launches, no graphs)."""
@@ -210,6 +247,27 @@ def mixed_batching(count=256, iters=30, seed=0):
             "speedup": t_solo / t_batch}
 
 
+def stream_ceiling(nbytes):
+    """Best rate of the library's streaming copy (equal HBM reads and writes) over a few
+    grid sizes, for `nbytes` each way: the practical ceiling of the multiplier stream."""
+    import torch
+    from paper_2011_04240_amd import mato
+    nbytes -= nbytes % 16
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    best = None
+    for grid in (1024, 2048, 4096, 16384, 65536):
+        ms = mato.mato_stream_copy(src, dst, nbytes, grid, 10)
+        gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+        if best is None or gbs > best[0]:
+            best = (gbs, grid, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": best[0], "grid": best[1], "ms_per_copy": best[2], "bytes_each_way": nbytes}
+
+
 def copy_calibration(mib):
     import torch
     x = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
@@ -250,7 +308,7 @@ def main():
     torch.cuda.set_device(0)
     starts, goals = zip(*[sc.random_box(n, seed=q) for q in range(B)])
     t0 = time.perf_counter()
-    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, args.precision)
+    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, args.precision, solve=args.solve)
     plan_s = time.perf_counter() - t0
     batch = mato.Batch([plan] * B, starts, goals)
     tiles = batch.autotune() if not args.no_autotune else batch.get_tiles()
@@ -270,6 +328,8 @@ def main():
     alg_bytes = BYTES_PER_UPDATE * npairs * T * B
     achieved = alg_bytes / pw_avg_s / 1e9
     traffic = traffic_from_counters() if (n, T, B) == (64, 100, 1024) else None
+    batch.timing(False)
+    stream = stream_ceiling(alg_bytes // 2)
     r_max, _, _ = batch.residuals(0)
     out = {
         "metric": "pair-timestep updates/s at n=64,T=100",
@@ -285,22 +345,26 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "random-box problems, n=%d agents, T=%d instants, %d problems per launch" % (n, T, B),
-                   "n": n, "T": T, "problems": B, "precision": args.precision,
+                   "n": n, "T": T, "problems": B, "precision": args.precision, "solve": args.solve,
                    "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]},
                    "device_ms_per_step": total_ms / args.steps, "plan_s": plan_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "stream_copy": stream, "frac_of_stream_copy": achieved / stream["GBps"]},
         "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
     }
     batch.close()
-    out["structured_step"] = structured_step(n, T, B, starts, goals, args)
+    if args.solve == "dense":
+        out["structured_step"] = structured_step(n, T, B, starts, goals, args)
     if not args.no_serve:
         out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve)
     if not args.no_mixed:
         out["mixed_batching"] = mixed_batching()
+    if not args.no_obstacles:
+        out["obstacle_scaling"] = obstacle_scaling()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds)
     print(json.dumps(out))

@@ -324,10 +324,25 @@ mato_status mato_server_run_trace(mato_server s, int32_t count, const double* ar
 typedef struct mato_batch_s* mato_solve;
 mato_status mato_solve_run(mato_plan plan, const double* starts, const double* goals,
                            int32_t iters, double tol, int32_t check_every, mato_solve* out);
+mato_status mato_solve_sync(mato_solve s);
 mato_status mato_solve_coeffs(mato_solve s, double* c);
 mato_status mato_residuals(mato_solve s, double* r_max, double* r_rms, double* cost,
                            int32_t cap, int32_t* n_written);
+/* k more iterations (asynchronous, graph-replayed), as mato_batch_step with tol = 0. */
+mato_status mato_step(mato_solve s, int32_t k_steps);
+/* State hooks of the single problem, as mato_batch_get_state / mato_batch_set_state. */
+mato_status mato_get_state(mato_solve s, void* c, void* lambda, void* proj, void* d, void* X);
+mato_status mato_set_state(mato_solve s, const void* c, const void* lambda, const void* proj);
 void        mato_solve_destroy(mato_solve s);
+
+/* ---------------------------------------------------------- measurement ---
+ * Not part of the method: `iters` timed launches (after one warm-up) of a streaming
+ * copy of `bytes` from src to dst (device buffers, 16-byte aligned, bytes a multiple
+ * of 16; `grid` workgroups of 256 threads, 16-byte nontemporal loads and stores).
+ * Writes the mean time of one copy.  It is the practical ceiling for a stream with
+ * equal reads and writes, beside the vendor peak, for the pairwise stage's roofline. */
+mato_status mato_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, int32_t iters,
+                             void* hip_stream, double* ms_per_copy);
 
 #ifdef __cplusplus
 }

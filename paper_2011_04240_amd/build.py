@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmato.so")
-SOURCES = ["plan.hip", "kernels.hip", "gemm.hip", "batch.hip", "server.hip"]
+SOURCES = ["plan.hip", "kernels.hip", "gemm.hip", "batch.hip", "server.hip", "probe.hip"]
 ARCH = os.environ.get("MATO_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -306,7 +306,8 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     ctrl[3] = 1;
     ctrl[4] = 0;
     MATO_HIP(hipMemcpy(B->dctrl + kCtrl * q, ctrl, sizeof(ctrl), hipMemcpyHostToDevice));
-    MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->common_nv(), B->stream));
+    MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->common_nv(), true,
+                                B->stream));
     MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(hipStreamSynchronize(B->stream));
@@ -441,6 +442,18 @@ extern "C" mato_status mato_solve_coeffs(mato_solve s, double* c) { return mato_
 extern "C" mato_status mato_residuals(mato_solve s, double* r_max, double* r_rms, double* cost, int32_t cap,
                                       int32_t* n_written) {
     return mato_batch_residuals(s, 0, r_max, r_rms, cost, cap, n_written);
+}
+
+extern "C" mato_status mato_solve_sync(mato_solve s) { return mato_batch_sync(s); }
+
+extern "C" mato_status mato_step(mato_solve s, int32_t k_steps) { return mato_batch_step(s, k_steps, 0.0, 1); }
+
+extern "C" mato_status mato_get_state(mato_solve s, void* c, void* lambda, void* proj, void* d, void* X) {
+    return mato_batch_get_state(s, 0, c, lambda, proj, d, X);
+}
+
+extern "C" mato_status mato_set_state(mato_solve s, const void* c, const void* lambda, const void* proj) {
+    return mato_batch_set_state(s, 0, c, lambda, proj);
 }
 
 extern "C" void mato_solve_destroy(mato_solve s) { mato_batch_destroy(s); }

@@ -27,7 +27,7 @@
 namespace mato {
 
 template <typename S>
-hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int, size_t, int, hipStream_t);
+hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int, size_t, int, bool, hipStream_t);
 template <typename S>
 hipError_t set_pairwise_lds_limit(size_t);
 template <typename S>
@@ -128,6 +128,7 @@ struct Engine {
     GemmCol* dcolsr = nullptr;
     size_t cap_groups = 0, cap_tiles = 0, cap_colsq = 0, cap_colsr = 0;
     bool lists_dirty = true;
+    bool has_obs = false;                    // some active slot has static obstacles
 
     double tol = 0.0;
     bool debug = false;
@@ -333,6 +334,8 @@ struct Engine {
     mato_status rebuild_lists() {
         hitems.clear();
         size_t maxlds = 0;
+        has_obs = false;
+        for (const auto& P : probs) has_obs = has_obs || (P.active && P.n_obs > 0);
         for (int q = 0; q < count(); ++q)
             if (probs[q].active) slot_items(q, hitems, &maxlds, q);
         lds = maxlds;
@@ -531,7 +534,7 @@ struct Engine {
         MATO_HIP(launch_init<S>(ddesc, dk0c, count(), stream));
         MATO_HIP(launch_ceq<S>(ddesc, dkinv, count(), stream));
         MATO_HIP(launch_positions<S>(ddesc, count(), kModeInit, nv, stream));
-        MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, nv, stream));
+        MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, nv, has_obs, stream));
         MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, nv, stream));
         return MATO_OK;
     }
@@ -552,7 +555,7 @@ struct Engine {
         MATO_HIP(launch_init<S>(d, dk0c + q, 1, stream));
         MATO_HIP(launch_ceq<S>(d, dkinv + q, 1, stream));
         MATO_HIP(launch_positions<S>(d, 1, kModeInit, nv, stream));
-        MATO_HIP(launch_pairwise<S>(dscratch, (int)items.size(), d, kModeInit, threads, std::max(l, lds), nv, stream));
+        MATO_HIP(launch_pairwise<S>(dscratch, (int)items.size(), d, kModeInit, threads, std::max(l, lds), nv, has_obs, stream));
         MATO_HIP(launch_qbuild<S>(d, 1, kModeInit, nv, stream));
         return MATO_OK;
     }
@@ -586,7 +589,7 @@ struct Engine {
             e = hipEventRecord(pw_events[pw_used], st);
             if (e != hipSuccess) return e;
         }
-        e = launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, st);
+        e = launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, has_obs, st);
         if (e != hipSuccess) return e;
         if (events) {
             e = hipEventRecord(pw_events[pw_used + 1], st);
@@ -793,11 +796,11 @@ struct Engine {
         for (int ipw : ipws)
             for (int thr : thrs) {
                 if (set_tiles(ipw, thr) != MATO_OK) continue;
-                MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, stream));
+                MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, has_obs, stream));
                 MATO_HIP(hipEventRecord(e0, stream));
                 const int reps = 5;
                 for (int r = 0; r < reps; ++r)
-                    MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, stream));
+                    MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeIter, threads, lds, nv, has_obs, stream));
                 MATO_HIP(hipEventRecord(e1, stream));
                 MATO_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;

@@ -95,7 +95,7 @@ struct Recip<double> {
 // >= n_pairs, between 64 and BLOCK).  A lane owns U pairs of a chunk and walks its
 // group's instants; the multipliers of the next (chunk, instant) are loaded while the
 // current one is computed, and the first ones before the positions are staged.
-template <typename S, int BLOCK, int NV, int MODE>
+template <typename S, int BLOCK, int NV, int MODE, bool OBS>
 __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restrict__ items,
                                                          const ProblemDesc<S>* __restrict__ probs) {
     constexpr int U = 4;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     gptr<const int> ctrl = glob((const int*)Dp->ctrl);
     if (!ctrl[3]) return;                          // inactive slot
     if (MODE == kModeIter && ctrl[1]) return;      // converged
-    const int n = Dp->n, np = Dp->np, n_obs = Dp->n_obs;
+    const int n = Dp->n, np = Dp->np, n_obs = OBS ? Dp->n_obs : 0;   // OBS: some problem has obstacles
     const int t0 = it.t0, tc = it.tc;
     gptr<const S> Xm = glob((const S*)Dp->X);
     gptr<const unsigned> pairs = glob(Dp->pairs);
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
             // partner: agent j, or (rows after the pairs) static obstacle j - n with its own axes
             S xj, yj, zj, ia2p = ia2, ib2p = ib2, lzp = lzl;
-            if (j < n) {
+            if (!OBS || j < n) {
                 xj = X[j];
                 yj = X[n + j];
                 zj = X[2 * n + j];
@@ -333,10 +333,11 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
     gptr<const double> Pddm = glob(Dp->Pdd);
     gptr<const double> cm = glob((const double*)Dp->c);
     gptr<S> Xm = glob(Dp->X);
-    constexpr int TC = 32;
-    __shared__ double Ps[TC * kMaxCoef], Pdds[TC * kMaxCoef];
+    constexpr int kRows = 1536;                    // basis entries staged per chunk (12 KB each)
+    __shared__ double Ps[kRows], Pdds[kRows];
     __shared__ double red[3 * 4];
     const int n3 = 3 * n;
+    const int TC = kRows / nv;                     // instants per chunk (139 for 11 coefficients)
     double cost = 0.0;
     for (int tb = 0; tb < T; tb += TC) {
         const int tn = min(TC, T - tb);
@@ -353,7 +354,25 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
                 double cv[NV];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) cv[k] = ci[k];
-                for (int t = 0; t < tn; ++t) {
+                int t = 0;
+                // four instants at a time: eight independent FMA chains and their LDS
+                // reads in flight together (same k and t order as one at a time)
+                for (; t + 4 <= tn; t += 4) {
+                    double x[4] = {0.0, 0.0, 0.0, 0.0}, acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int k = 0; k < NV; ++k)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            x[u] += Ps[(t + u) * NV + k] * cv[k];
+                            acc[u] += Pdds[(t + u) * NV + k] * cv[k];
+                        }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        Xm[(size_t)(tb + t + u) * n3 + col] = (S)x[u];
+                        cost += acc[u] * acc[u];
+                    }
+                }
+                for (; t < tn; ++t) {
                     double x = 0.0, acc = 0.0;
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
@@ -401,21 +420,34 @@ __global__ __launch_bounds__(256) void solve_positions_kernel(const ProblemDesc<
     gptr<const int> ctrl = glob((const int*)Dp->ctrl);
     if (!ctrl[3] || ctrl[1]) return;
     const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, ldq = Dp->ldq, ldc = Dp->ldc;
+    constexpr int kGroups = 8;                      // agent groups of the partial sums of g
     __shared__ double M[2 * kMaxCoef * kMaxCoef];
+    __shared__ double part[kGroups * kAxes * kMaxCoef];
     __shared__ double gm[kAxes * kMaxCoef], h[kAxes * kMaxCoef];
     gptr<const double> Sm = glob(Dp->smat);
     for (int e = threadIdx.x; e < 2 * nv * nv; e += blockDim.x) M[e] = Sm[e];
     gptr<const double> q = glob((const double*)Dp->q);
-    const double inv_n = 1.0 / (double)n;
-    for (int o = threadIdx.x; o < kAxes * nv; o += blockDim.x) {
-        const int a = o / nv, k = o - a * nv;
+    const int m3 = kAxes * nv;
+    const int ng = max(1, min(kGroups, (int)blockDim.x / m3));
+    // g_mean: agents i = grp, grp + ng, ... summed per group, then the groups in order
+    for (int o = threadIdx.x; o < ng * m3; o += blockDim.x) {
+        const int grp = o / m3, ak = o - grp * m3;
+        const int a = ak / nv, k = ak - a * nv;
         gptr<const double> qa = q + (size_t)a * ldq + k;
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += qa[(size_t)i * nv];
-        gm[o] = s * inv_n;
+        double sacc = 0.0;
+#pragma unroll 4
+        for (int i = grp; i < n; i += ng) sacc += qa[(size_t)i * nv];
+        part[grp * m3 + ak] = sacc;
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < kAxes * nv; o += blockDim.x) {
+    const double inv_n = 1.0 / (double)n;
+    for (int o = threadIdx.x; o < m3; o += blockDim.x) {
+        double sacc = 0.0;
+        for (int grp = 0; grp < ng; ++grp) sacc += part[grp * m3 + o];
+        gm[o] = sacc * inv_n;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < m3; o += blockDim.x) {
         const int a = o / nv, k = o - a * nv;
         double v = 0.0;
         for (int l = 0; l < nv; ++l) v += M[nv * nv + k * nv + l] * gm[a * nv + l];
@@ -424,17 +456,20 @@ __global__ __launch_bounds__(256) void solve_positions_kernel(const ProblemDesc<
     __syncthreads();
     gptr<double> c = glob(Dp->c);
     gptr<const double> ceq = glob((const double*)Dp->ceq);
-    for (int col = threadIdx.x; col < kAxes * n; col += blockDim.x) {
-        const int a = col / n, i = col - a * n;
+    const int nc = n * nv;
+    for (int o = threadIdx.x; o < kAxes * nc; o += blockDim.x) {      // one output coefficient each
+        const int a = o / nc, rem = o - a * nc;
+        const int i = rem / nv, k = rem - i * nv;
         gptr<const double> gi = q + (size_t)a * ldq + (size_t)i * nv;
-        const size_t o = (size_t)a * ldc + (size_t)i * nv;
-        double g[NV > 0 ? NV : kMaxCoef];
-        for (int l = 0; l < nv; ++l) g[l] = gi[l];
-        for (int k = 0; k < nv; ++k) {
-            double v = 0.0;
-            for (int l = 0; l < nv; ++l) v += M[k * nv + l] * g[l];
-            c[o + k] = ceq[o + k] + h[a * nv + k] + v;
+        double v = 0.0;
+        if constexpr (NV > 0) {
+#pragma unroll
+            for (int l = 0; l < NV; ++l) v += M[k * NV + l] * gi[l];
+        } else {
+            for (int l = 0; l < nv; ++l) v += M[k * nv + l] * gi[l];
         }
+        const size_t oc = (size_t)a * ldc + rem;
+        c[oc] = ceq[oc] + h[a * nv + k] + v;
     }
     __syncthreads();                       // c is read back by other threads of this workgroup
     positions_body<S, NV>(Dp);
@@ -458,35 +493,65 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
     gptr<double> q = glob(Dp->q);
     gptr<float> qf = glob(Dp->qf);
     const int n3 = 3 * n;
-    for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+    if constexpr (NV > 0) {
+        // A thread owns columns tid and tid + 256 (3n <= 480); the basis rows are staged in
+        // LDS in chunks and each column's S values are loaded 8 instants at a time.
+        static_assert(3 * MATO_MAX_AGENTS <= 512, "two columns per thread of a 256-thread workgroup");
+        constexpr int kRows = 2048;
+        constexpr int TC = kRows / NV;
+        __shared__ double Ps[kRows];
+        double acc[2][NV];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[h][k] = 0.0;
+        for (int tb = 0; tb < T; tb += TC) {
+            const int tn = min(TC, T - tb);
+            __syncthreads();
+            for (int e = threadIdx.x; e < tn * NV; e += blockDim.x) Ps[e] = Pm[(size_t)tb * NV + e];
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int col = threadIdx.x + h * 256;
+                if (col >= n3) continue;
+                gptr<const S> sp = ss + (size_t)tb * n3 + col;     // [(t*3 + a)*n + i] = t*3n + col
+                int t = 0;
+                for (; t + 8 <= tn; t += 8) {
+                    S sv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sv[u] = sp[(size_t)(t + u) * n3];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const double su = (double)sv[u];
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) acc[h][k] += Ps[(t + u) * NV + k] * su;
+                    }
+                }
+                for (; t < tn; ++t) {
+                    const double sv = (double)sp[(size_t)t * n3];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) acc[h][k] += Ps[t * NV + k] * sv;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int col = threadIdx.x + h * 256;
+            if (col >= n3) continue;
+            const int a = col / n, i = col - a * n;
+            const size_t o = (size_t)a * ldq + (size_t)i * nv;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                q[o + k] = rho * acc[h][k];
+                qf[o + k] = (float)(rho * acc[h][k]);
+            }
+        }
+    } else {
+      for (int col = threadIdx.x; col < n3; col += blockDim.x) {
         const int a = col / n, i = col - a * n;
         gptr<const S> sp = ss + col;                 // [(t*3 + a)*n + i] = t*3n + col
         const size_t o = (size_t)a * ldq + (size_t)i * nv;
-        if constexpr (NV > 0) {
-            double acc[NV];
-#pragma unroll
-            for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-            int t = 0;
-            for (; t + 8 <= T; t += 8) {
-                double sv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sv[u] = (double)sp[(size_t)(t + u) * n3];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) acc[k] += Pm[(size_t)(t + u) * NV + k] * sv[u];
-            }
-            for (; t < T; ++t) {
-                const double sv = (double)sp[(size_t)t * n3];
-#pragma unroll
-                for (int k = 0; k < NV; ++k) acc[k] += Pm[(size_t)t * NV + k] * sv;
-            }
-#pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                q[o + k] = rho * acc[k];
-                qf[o + k] = (float)(rho * acc[k]);
-            }
-        } else {
+        {
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
                 for (int t = 0; t < T; ++t) acc += Pm[(size_t)t * nv + k] * (double)sp[(size_t)t * n3];
@@ -494,16 +559,21 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
                 qf[o + k] = (float)(rho * acc);
             }
         }
+      }
     }
-    if (mode == kModeIter && threadIdx.x == 0) {
+    if (mode == kModeIter) {
+        // residual partials of the pairwise work items: strided per thread, then a fixed tree
         gptr<const double> part = glob((const double*)Dp->part);
-        gptr<double> hist = glob(Dp->hist);
         const int nslab = Dp->nslab;
-        double mx = 0.0, s1 = 0.0;
-        for (int k = 0; k < nslab; ++k) {
+        double mx = 0.0, s1 = 0.0, z = 0.0;
+        for (int k = threadIdx.x; k < nslab; k += blockDim.x) {
             mx = fmax(mx, part[(size_t)k * 4 + 0]);
             s1 += part[(size_t)k * 4 + 1];
         }
+        __shared__ double red[3 * 4];
+        block_reduce3<double, 256>(mx, s1, z, red);
+        if (threadIdx.x != 0) return;
+        gptr<double> hist = glob(Dp->hist);
         const double s2 = glob((const double*)Dp->misc)[0];
         const int itn = ctrl[0];
         const double rmax = sqrt(mx);
@@ -633,59 +703,63 @@ __global__ __launch_bounds__(256) void init_kernel(const ProblemDesc<S>* __restr
 }
 
 // ------------------------------------------------------------- launchers ---
-template <typename S, int NV, int MODE>
+template <typename S, int NV, int MODE, bool OBS>
 static hipError_t launch_pw(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int threads,
                             size_t lds, hipStream_t st) {
     switch (threads) {
         case 256:
-            pairwise_kernel<S, 256, NV, MODE><<<nitems, 256, lds, st>>>(items, probs);
+            pairwise_kernel<S, 256, NV, MODE, OBS><<<nitems, 256, lds, st>>>(items, probs);
             break;
         case 512:
-            pairwise_kernel<S, 512, NV, MODE><<<nitems, 512, lds, st>>>(items, probs);
+            pairwise_kernel<S, 512, NV, MODE, OBS><<<nitems, 512, lds, st>>>(items, probs);
             break;
         default:
-            pairwise_kernel<S, 1024, NV, MODE><<<nitems, 1024, lds, st>>>(items, probs);
+            pairwise_kernel<S, 1024, NV, MODE, OBS><<<nitems, 1024, lds, st>>>(items, probs);
             break;
     }
     return hipGetLastError();
 }
 
 template <typename S, int NV>
-static hipError_t launch_pw_mode(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
+static hipError_t launch_pw_mode(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode, bool obs,
                                  int threads, size_t lds, hipStream_t st) {
-    if (mode == kModeIter) return launch_pw<S, NV, kModeIter>(items, nitems, probs, threads, lds, st);
-    if (mode == kModeInit) return launch_pw<S, NV, kModeInit>(items, nitems, probs, threads, lds, st);
-    return launch_pw<S, NV, kModeSetState>(items, nitems, probs, threads, lds, st);
+    if (mode == kModeIter)
+        return obs ? launch_pw<S, NV, kModeIter, true>(items, nitems, probs, threads, lds, st)
+                   : launch_pw<S, NV, kModeIter, false>(items, nitems, probs, threads, lds, st);
+    if (mode == kModeInit) return launch_pw<S, NV, kModeInit, true>(items, nitems, probs, threads, lds, st);
+    return launch_pw<S, NV, kModeSetState, true>(items, nitems, probs, threads, lds, st);
 }
 
 // nv: the (common) number of basis coefficients of the launch's problems, or 0 if they differ.
 template <typename S>
 hipError_t launch_pairwise(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
-                           int threads, size_t lds, int nv, hipStream_t st) {
+                           int threads, size_t lds, int nv, bool obs, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, threads, lds, st);
-    return launch_pw_mode<S, 0>(items, nitems, probs, mode, threads, lds, st);
+    if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, obs, threads, lds, st);
+    return launch_pw_mode<S, 0>(items, nitems, probs, mode, obs, threads, lds, st);
 }
 
-template <typename S, int NV, int MODE>
+template <typename S, int NV, int MODE, bool OBS>
 static hipError_t set_lds_one(size_t lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 256, NV, MODE>,
+    hipError_t e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 256, NV, MODE, OBS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 512, NV, MODE>,
+    e = hipFuncSetAttribute((const void*)pairwise_kernel<S, 512, NV, MODE, OBS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)pairwise_kernel<S, 1024, NV, MODE>,
+    return hipFuncSetAttribute((const void*)pairwise_kernel<S, 1024, NV, MODE, OBS>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename S, int NV>
 static hipError_t set_lds_nv(size_t lds) {
-    hipError_t e = set_lds_one<S, NV, kModeIter>(lds);
+    hipError_t e = set_lds_one<S, NV, kModeIter, false>(lds);
     if (e != hipSuccess) return e;
-    e = set_lds_one<S, NV, kModeInit>(lds);
+    e = set_lds_one<S, NV, kModeIter, true>(lds);
     if (e != hipSuccess) return e;
-    return set_lds_one<S, NV, kModeSetState>(lds);
+    e = set_lds_one<S, NV, kModeInit, true>(lds);
+    if (e != hipSuccess) return e;
+    return set_lds_one<S, NV, kModeSetState, true>(lds);
 }
 
 template <typename S>
@@ -746,8 +820,10 @@ hipError_t launch_init(const ProblemDesc<S>* probs, const double* const* k0c, in
     return hipGetLastError();
 }
 
-template hipError_t launch_pairwise<float>(const WorkItem*, int, const ProblemDesc<float>*, int, int, size_t, int, hipStream_t);
-template hipError_t launch_pairwise<double>(const WorkItem*, int, const ProblemDesc<double>*, int, int, size_t, int, hipStream_t);
+template hipError_t launch_pairwise<float>(const WorkItem*, int, const ProblemDesc<float>*, int, int, size_t, int, bool,
+                                          hipStream_t);
+template hipError_t launch_pairwise<double>(const WorkItem*, int, const ProblemDesc<double>*, int, int, size_t, int, bool,
+                                           hipStream_t);
 template hipError_t set_pairwise_lds_limit<float>(size_t);
 template hipError_t set_pairwise_lds_limit<double>(size_t);
 template hipError_t launch_qbuild<float>(const ProblemDesc<float>*, int, int, int, hipStream_t);

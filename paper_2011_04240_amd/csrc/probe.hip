@@ -1,0 +1,44 @@
+// Measurement utility of libmato: a streaming copy kernel (equal HBM reads and writes,
+// 16-byte nontemporal accesses, grid-stride), the practical ceiling against which the
+// pairwise stage's multiplier stream (12 bytes read and 12 written per pair-instant)
+// is compared.  Not part of the method.
+#include "common.h"
+
+namespace mato {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(const v4f* __restrict__ src, v4f* __restrict__ dst,
+                                                          size_t n4) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+}  // namespace mato
+
+using namespace mato;
+
+extern "C" mato_status mato_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, int32_t iters,
+                                        void* hip_stream, double* ms_per_copy) {
+    if (!src || !dst || !ms_per_copy || bytes < 16 || bytes % 16 != 0 || grid < 1 || iters < 1 ||
+        (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) {
+        set_error("stream copy: 16-byte aligned buffers, bytes a positive multiple of 16, grid and iters >= 1");
+        return MATO_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t n4 = (size_t)bytes / 16;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MATO_HIP(hipEventCreate(&e0));
+    MATO_HIP(hipEventCreate(&e1));
+    stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);   // warm-up
+    MATO_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < iters; ++r) stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);
+    MATO_HIP(hipEventRecord(e1, st));
+    MATO_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_copy = (double)ms / iters;
+    return MATO_OK;
+}

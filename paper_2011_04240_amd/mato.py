@@ -106,6 +106,11 @@ SIGNATURES = {
     "mato_solve_coeffs": (_i32, [_vp, _vp]),
     "mato_residuals": (_i32, [_vp, _vp, _vp, _vp, _i32, _pi32]),
     "mato_solve_destroy": (None, [_vp]),
+    "mato_solve_sync": (_i32, [_vp]),
+    "mato_step": (_i32, [_vp, _i32]),
+    "mato_get_state": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
+    "mato_stream_copy": (_i32, [_vp, _vp, ctypes.c_int64, _i32, _i32, _vp, _pf64]),
 }
 
 
@@ -353,6 +358,49 @@ def mato_server_run_trace(server, arrival_s, ns, starts, goals, latency, iters, 
     _check(lib().mato_server_run_trace(server, len(ns), _ptr(arrival_s), _ptr(ns), _ptr(starts), _ptr(goals),
                                        _ptr(latency), _ptr(iters), _ptr(converged), ctypes.byref(wall)))
     return wall.value
+
+
+# ---------------------------------------------------- single-problem wrappers ---
+def mato_solve_run(plan, starts, goals, iters, tol=0.0, check_every=10):
+    h = ctypes.c_void_p()
+    status = _check(lib().mato_solve_run(plan, _ptr(starts), _ptr(goals), iters, tol, check_every, ctypes.byref(h)))
+    return h, status
+
+
+def mato_solve_sync(solve):
+    _check(lib().mato_solve_sync(solve))
+
+
+def mato_step(solve, k):
+    _check(lib().mato_step(solve, k))
+
+
+def mato_solve_coeffs(solve, out):
+    _check(lib().mato_solve_coeffs(solve, _ptr(out)))
+
+
+def mato_residuals(solve, r_max, r_rms, cost, cap):
+    nw = _i32()
+    _check(lib().mato_residuals(solve, _ptr(r_max), _ptr(r_rms), _ptr(cost), cap, ctypes.byref(nw)))
+    return nw.value
+
+
+def mato_get_state(solve, c=None, lam=None, proj=None, d=None, X=None):
+    _check(lib().mato_get_state(solve, _ptr(c), _ptr(lam), _ptr(proj), _ptr(d), _ptr(X)))
+
+
+def mato_set_state(solve, c, lam, proj):
+    _check(lib().mato_set_state(solve, _ptr(c), _ptr(lam), _ptr(proj)))
+
+
+def mato_solve_destroy(solve):
+    lib().mato_solve_destroy(solve)
+
+
+def mato_stream_copy(src, dst, nbytes, grid=1024, iters=10, stream=None):
+    ms = _f64()
+    _check(lib().mato_stream_copy(_ptr(src), _ptr(dst), nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 # ---------------------------------------------------------------- owners ---

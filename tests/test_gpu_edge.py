@@ -189,3 +189,41 @@ def test_mixed_solve_kinds_rejected():
     with pytest.raises(mato.MatoError) as e:
         b.set_rho_schedule([[pd], [ps]], [0, 10])
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
+
+
+def test_single_problem_api():
+    """mato_solve_run / mato_step / state hooks give what a batch of one gives."""
+    say("single-problem api")
+    s, g = sc.swap_circle(4, seed=2)
+    p = mato.Plan(4, 50, 11, 5.0, 0.4, 0.8, 1.0, "fp32")
+    h, status = mato.mato_solve_run(p.handle, np.ascontiguousarray(s), np.ascontiguousarray(g), 20, 0.0, 5)
+    assert status in (mato.MATO_OK, mato.MATO_WARN_NOT_CONVERGED)
+    mato.mato_step(h, 7)
+    mato.mato_solve_sync(h)
+    b = mato.Batch([p], [s], [g])
+    b.step(27)
+    c = np.empty((4, 3, 11))
+    mato.mato_solve_coeffs(h, c)
+    np.testing.assert_array_equal(c, b.coeffs(0))
+    r_max = np.empty(27)
+    assert mato.mato_residuals(h, r_max, None, None, 27) == 27
+    np.testing.assert_array_equal(r_max, b.residuals(0)[0])
+    lam = np.empty((6, 50, 3), np.float32)
+    mato.mato_get_state(h, c, lam)
+    np.testing.assert_array_equal(lam, b.get_state(0)["lam"])
+    # resume a second solve from the first one's state: same next iterate
+    mato.lib().mato_batch_debug(h, 1)
+    mato.mato_step(h, 1)
+    proj = np.empty((6, 50, 3), np.float32)
+    c1, lam1 = np.empty((4, 3, 11)), np.empty((6, 50, 3), np.float32)
+    mato.mato_get_state(h, c1, lam1, proj)
+    h2, _ = mato.mato_solve_run(p.handle, np.ascontiguousarray(s), np.ascontiguousarray(g), 0, 0.0, 1)
+    mato.mato_set_state(h2, c1, lam1, proj)
+    mato.mato_step(h, 3)
+    mato.mato_step(h2, 3)
+    c2, c3 = np.empty((4, 3, 11)), np.empty((4, 3, 11))
+    mato.mato_solve_coeffs(h, c2)
+    mato.mato_solve_coeffs(h2, c3)
+    np.testing.assert_array_equal(c2, c3)
+    mato.mato_solve_destroy(h)
+    mato.mato_solve_destroy(h2)
