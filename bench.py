@@ -250,21 +250,14 @@ def mixed_batching(count=256, iters=30, seed=0):
 def stream_ceiling(nbytes):
     """Best rate of the library's streaming copy (equal HBM reads and writes) over a few
     grid sizes, for `nbytes` each way: the practical ceiling of the multiplier stream."""
-    import torch
     from paper_2011_04240_amd import mato
     nbytes -= nbytes % 16
-    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    src.fill_(1.0)
-    torch.cuda.synchronize()
     best = None
     for grid in (1024, 2048, 4096, 16384, 65536):
-        ms = mato.mato_stream_copy(src, dst, nbytes, grid, 10)
+        ms = mato.mato_stream_copy(nbytes, grid, 10)
         gbs = 2 * nbytes / (ms * 1e-3) / 1e9
         if best is None or gbs > best[0]:
             best = (gbs, grid, ms)
-    del src, dst
-    torch.cuda.empty_cache()
     return {"GBps": best[0], "grid": best[1], "ms_per_copy": best[2], "bytes_each_way": nbytes}
 
 

@@ -336,13 +336,14 @@ mato_status mato_set_state(mato_solve s, const void* c, const void* lambda, cons
 void        mato_solve_destroy(mato_solve s);
 
 /* ---------------------------------------------------------- measurement ---
- * Not part of the method: `iters` timed launches (after one warm-up) of a streaming
- * copy of `bytes` from src to dst (device buffers, 16-byte aligned, bytes a multiple
- * of 16; `grid` workgroups of 256 threads, 16-byte nontemporal loads and stores).
- * Writes the mean time of one copy.  It is the practical ceiling for a stream with
- * equal reads and writes, beside the vendor peak, for the pairwise stage's roofline. */
-mato_status mato_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, int32_t iters,
-                             void* hip_stream, double* ms_per_copy);
+ * Not part of the method: allocates two device buffers of `bytes` (a positive multiple
+ * of 16), fills the source, and times `iters` launches (after one warm-up) of a
+ * streaming copy between them (`grid` workgroups of 256 threads, 16-byte nontemporal
+ * loads and stores); checks the first and last 64 KiB of the copy and frees both
+ * buffers.  Writes the mean time of one copy: the practical ceiling for a stream with
+ * equal reads and writes, beside the vendor peak, for the pairwise stage's roofline.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (also if the copy differs). */
+mato_status mato_stream_copy(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream, double* ms_per_copy);
 
 #ifdef __cplusplus
 }

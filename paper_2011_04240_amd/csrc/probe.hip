@@ -4,6 +4,8 @@
 // is compared.  Not part of the method.
 #include "common.h"
 
+#include <algorithm>
+
 namespace mato {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -18,27 +20,50 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(const v4f* __restrict_
 
 using namespace mato;
 
-extern "C" mato_status mato_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, int32_t iters,
-                                        void* hip_stream, double* ms_per_copy) {
-    if (!src || !dst || !ms_per_copy || bytes < 16 || bytes % 16 != 0 || grid < 1 || iters < 1 ||
-        (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) {
-        set_error("stream copy: 16-byte aligned buffers, bytes a positive multiple of 16, grid and iters >= 1");
+extern "C" mato_status mato_stream_copy(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream,
+                                        double* ms_per_copy) {
+    if (!ms_per_copy || bytes < 16 || bytes % 16 != 0 || grid < 1 || iters < 1) {
+        set_error("stream copy: bytes a positive multiple of 16, grid and iters >= 1");
         return MATO_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t n4 = (size_t)bytes / 16;
+    void *src = nullptr, *dst = nullptr;
+    if (hipMalloc(&src, (size_t)bytes) != hipSuccess || hipMalloc(&dst, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(src);
+        set_error("device allocation of 2 x %lld bytes failed", (long long)bytes);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    MATO_HIP(hipEventCreate(&e0));
-    MATO_HIP(hipEventCreate(&e1));
-    stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);   // warm-up
-    MATO_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < iters; ++r) stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);
-    MATO_HIP(hipEventRecord(e1, st));
-    MATO_HIP(hipEventSynchronize(e1));
+    mato_status status = MATO_OK;
     float ms = 0.0f;
-    MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *ms_per_copy = (double)ms / iters;
-    return MATO_OK;
+    std::vector<unsigned char> head(std::min<size_t>((size_t)bytes, 65536)), tail(head.size());
+    auto run = [&]() -> mato_status {
+        MATO_HIP(hipMemsetAsync(src, 0x5a, (size_t)bytes, st));
+        MATO_HIP(hipMemsetAsync(dst, 0, (size_t)bytes, st));
+        MATO_HIP(hipEventCreate(&e0));
+        MATO_HIP(hipEventCreate(&e1));
+        stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);   // warm-up
+        MATO_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < iters; ++r) stream_copy_kernel<<<grid, 256, 0, st>>>((const v4f*)src, (v4f*)dst, n4);
+        MATO_HIP(hipEventRecord(e1, st));
+        MATO_HIP(hipEventSynchronize(e1));
+        MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
+        MATO_HIP(hipMemcpy(head.data(), dst, head.size(), hipMemcpyDeviceToHost));
+        MATO_HIP(hipMemcpy(tail.data(), (char*)dst + (bytes - (int64_t)tail.size()), tail.size(), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < head.size(); ++k)
+            if (head[k] != 0x5a || tail[k] != 0x5a) {
+                set_error("stream copy: destination differs from the source");
+                return MATO_ERR_HIP;
+            }
+        return MATO_OK;
+    };
+    status = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(src);
+    dfree(dst);
+    if (status == MATO_OK) *ms_per_copy = (double)ms / iters;
+    return status;
 }

@@ -110,7 +110,7 @@ SIGNATURES = {
     "mato_step": (_i32, [_vp, _i32]),
     "mato_get_state": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
-    "mato_stream_copy": (_i32, [_vp, _vp, ctypes.c_int64, _i32, _i32, _vp, _pf64]),
+    "mato_stream_copy": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
 }
 
 
@@ -397,9 +397,9 @@ def mato_solve_destroy(solve):
     lib().mato_solve_destroy(solve)
 
 
-def mato_stream_copy(src, dst, nbytes, grid=1024, iters=10, stream=None):
+def mato_stream_copy(nbytes, grid=1024, iters=10, stream=None):
     ms = _f64()
-    _check(lib().mato_stream_copy(_ptr(src), _ptr(dst), nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
+    _check(lib().mato_stream_copy(nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
     return ms.value
 
 

@@ -227,3 +227,12 @@ def test_single_problem_api():
     np.testing.assert_array_equal(c2, c3)
     mato.mato_solve_destroy(h)
     mato.mato_solve_destroy(h2)
+
+
+def test_stream_copy_probe():
+    say("stream copy probe")
+    ms = mato.mato_stream_copy(1 << 24, 256, 3)
+    assert ms > 0
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_stream_copy(15, 256, 1)
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
