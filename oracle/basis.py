@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 The paper writes each position component as a linear map of basis
 coefficients, x_i = P c_{x_i}, with velocity P-dot c and acceleration
-P-ddot c, and leaves the basis open ("e.g. polynomials").  The reading used
+P-ddot c, and leaves the basis open (polynomials are one example).  The reading used
 here: a Bernstein basis of degree n_coef-1 on normalised time tau in [0, 1],
 sampled at T uniformly spaced instants that include both end points
 (tau_k = k/(T-1), t_k = t_final * tau_k).  Derivatives are taken in physical
