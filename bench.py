@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--serve-solve", default="structured", choices=["dense", "structured"])
     ap.add_argument("--sweep-requests", type=int, default=2000,
                     help="requests per rate in the sweep (fewer where the trace would exceed 90 s)")
+    ap.add_argument("--serve-graphs", action="store_true",
+                    help="replay the server's iterations from HIP graphs (recaptured when the resident set changes)")
     ap.add_argument("--serve-fixed-rho", action="store_true",
                     help="serve with one rho instead of the increasing schedule")
     return ap.parse_args()
@@ -122,7 +124,7 @@ RHO_SCHEDULE = ([2.0 ** j for j in range(10)], [30 * j for j in range(10)])
 
 
 def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_iters=2000, tol=1e-3,
-                schedule=True, solve="structured"):
+                schedule=True, solve="structured", use_graphs=False):
     """Poisson arrivals of random-box problems (n uniform over 4..128, box at the n=64
     density) replayed in real time through the server; latency = finish - arrival.
     With `schedule`, ten increasing rho (doubling every 30 iterations, Sec. IV-A)."""
@@ -134,7 +136,7 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
     arr = sc.poisson_arrivals(rate, count, seed=seed)
     srv = mato.Server(T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision=precision,
                       max_slots=max_slots, chunk=chunk, max_iters=max_iters, tol=tol,
-                      rho_schedule=RHO_SCHEDULE if schedule else None, solve=solve)
+                      rho_schedule=RHO_SCHEDULE if schedule else None, solve=solve, use_graphs=use_graphs)
     t0 = time.perf_counter()
     srv.warm(4, 128)
     warm_s = time.perf_counter() - t0
@@ -146,7 +148,7 @@ def serve_trace(rate, count, precision, seed=0, max_slots=256, chunk=10, max_ite
             "throughput_problems_per_s": count / wall, "updates_per_s": upd / wall,
             "converged_frac": float(np.mean(conv)), "capped_frac": float(np.mean(its >= max_iters)),
             "mean_iters": float(np.mean(its)), "wall_s": wall, "plan_warm_s": warm_s,
-            "precision": precision, "solve": solve, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol,
+            "precision": precision, "solve": solve, "graphs": use_graphs, "max_slots": max_slots, "chunk": chunk, "max_iters": max_iters, "tol_m": tol,
             "rho": ({"values": RHO_SCHEDULE[0], "start_iter": RHO_SCHEDULE[1]} if schedule else 1.0)}
 
 
@@ -286,7 +288,8 @@ def main():
         sweep = []
         for k, r in enumerate([10, 20, 50, 100, 200, 500]):
             sweep.append(serve_trace(r, min(args.sweep_requests, int(r * 90)), args.serve_precision, seed=k,
-                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve))
+                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve,
+                                     use_graphs=args.serve_graphs))
             print(f"rate {r}/s: p50 {sweep[-1]['p50_ms']:.1f} ms, p99 {sweep[-1]['p99_ms']:.1f} ms",
                   file=sys.stderr, flush=True)
         print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
@@ -353,7 +356,8 @@ def main():
         out["structured_step"] = structured_step(n, T, B, starts, goals, args)
     if not args.no_serve:
         out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
-                                    schedule=not args.serve_fixed_rho, solve=args.serve_solve)
+                                    schedule=not args.serve_fixed_rho, solve=args.serve_solve,
+                                    use_graphs=args.serve_graphs)
     if not args.no_mixed:
         out["mixed_batching"] = mixed_batching()
     if not args.no_obstacles:

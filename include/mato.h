@@ -277,6 +277,9 @@ typedef struct {
     int32_t    rho_start[MATO_MAX_STAGES];   /* first iteration of each stage: 0, then
                                                 increasing multiples of chunk            */
     int32_t    solve;                        /* mato_solve_kind of every plan             */
+    int32_t    use_graphs;                   /* 1: replay each step's iterations from HIP
+                                                graphs, recaptured when the resident set
+                                                changes; 0: launch them one by one        */
 } mato_server_config;
 
 /* Errors: INVALID_ARG (configuration out of range), OUT_OF_MEMORY, HIP. */

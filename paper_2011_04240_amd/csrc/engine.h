@@ -670,7 +670,17 @@ struct Engine {
         }
         if (moved.empty()) return MATO_OK;
         MATO_HIP(hipStreamSynchronize(stream));
-        MATO_TRY(rebuild_lists());
+        if (solve == MATO_SOLVE_STRUCTURED) {
+            // only the moved slots' descriptors change (rho, the per-agent inverses): the
+            // work lists and any captured graphs stay valid
+            for (int q : moved) {
+                fill_desc(q);
+                MATO_HIP(hipMemcpyAsync(ddesc + q, &hdesc[q], sizeof(ProblemDesc<S>), hipMemcpyHostToDevice, stream));
+            }
+            MATO_HIP(hipStreamSynchronize(stream));
+        } else {
+            MATO_TRY(rebuild_lists());        // the product groups follow the plans
+        }
         for (int q : moved) MATO_HIP(launch_ceq<S>(ddesc + q, dkinv + q, 1, stream));
         return MATO_OK;
     }

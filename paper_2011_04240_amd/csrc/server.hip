@@ -230,7 +230,7 @@ struct ServerOps {
         MATO_TRY(admit(s));
         Engine<S>* e = E(s);
         int act = e->active_count();
-        if (act > 0) MATO_TRY(e->step(s->cfg.chunk, s->cfg.tol, false));
+        if (act > 0) MATO_TRY(e->step(s->cfg.chunk, s->cfg.tol, s->cfg.use_graphs != 0));
         if (running) *running = act;
         if (queued) *queued = (int)s->queue.size();
         return MATO_OK;
@@ -274,7 +274,8 @@ extern "C" mato_status mato_server_create(const mato_server_config* cfg, void* h
         (cfg->precision != MATO_FP64 && cfg->precision != MATO_FP32 && cfg->precision != MATO_BF16_REFINED) ||
         (cfg->projection != 0 && cfg->projection != 1) || cfg->rho_stages < 0 || cfg->rho_stages > kMaxStages ||
         (cfg->solve != MATO_SOLVE_DENSE && cfg->solve != MATO_SOLVE_STRUCTURED) ||
-        (cfg->solve == MATO_SOLVE_STRUCTURED && cfg->precision == MATO_BF16_REFINED)) {
+        (cfg->solve == MATO_SOLVE_STRUCTURED && cfg->precision == MATO_BF16_REFINED) ||
+        (cfg->use_graphs != 0 && cfg->use_graphs != 1)) {
         set_error("invalid server configuration");
         return MATO_ERR_INVALID_ARG;
     }

@@ -55,7 +55,8 @@ class ServerConfig(ctypes.Structure):
                 ("rho", ctypes.c_double), ("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_double), ("chunk", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("projection", ctypes.c_int32), ("rho_stages", ctypes.c_int32),
-                ("rho_values", ctypes.c_double * 16), ("rho_start", ctypes.c_int32 * 16), ("solve", ctypes.c_int32)]
+                ("rho_values", ctypes.c_double * 16), ("rho_start", ctypes.c_int32 * 16), ("solve", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
 
 _lib = None
@@ -468,12 +469,13 @@ class Server:
 
     def __init__(self, T=100, n_coef=11, t_final=10.0, a=0.3, b=0.6, rho=1.0, precision="fp32", max_slots=64,
                  hbm_budget_bytes=0.0, chunk=10, max_iters=2000, tol=1e-3, shifted=False, rho_schedule=None,
-                 stream=None, solve="dense"):
+                 stream=None, solve="dense", use_graphs=False):
         self.T, self.n_coef = T, n_coef
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = ServerConfig(T, _Basis(0, n_coef, t_final), a, b, rho, self.precision, max_slots, hbm_budget_bytes,
                            chunk, max_iters, tol, int(bool(shifted)))
         cfg.solve = SOLVES[solve] if isinstance(solve, str) else int(solve)
+        cfg.use_graphs = int(bool(use_graphs))
         if rho_schedule is not None:
             values, starts = rho_schedule
             cfg.rho_stages = len(values)

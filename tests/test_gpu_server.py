@@ -47,13 +47,14 @@ def _drain(srv, ids, ns):
     raise AssertionError("server did not drain")
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_alone_vs_mix(precision):
-    say("server alone vs mix", precision)
+@pytest.mark.parametrize("precision,graphs", [("fp32", False), ("fp64", False), ("fp32", True)])
+def test_alone_vs_mix(precision, graphs):
+    say("server alone vs mix", precision, "graphs" if graphs else "eager")
     ns = [4, 17, 9, 30, 17, 6, 23, 12]
     scen = [sc.random_density_box(n, seed=200 + k) for k, n in enumerate(ns)]
     tol, cap = 1e-3, 600
-    srv = mato.Server(T=T, t_final=TF, a=A, b=B, precision=precision, max_slots=4, chunk=7, max_iters=cap, tol=tol)
+    srv = mato.Server(T=T, t_final=TF, a=A, b=B, precision=precision, max_slots=4, chunk=7, max_iters=cap, tol=tol,
+                      use_graphs=graphs)
     ids = [srv.submit(*scen[k]) for k in range(3)]
     srv.step()
     srv.step()
