@@ -173,6 +173,31 @@ def structured_step(n, T, B, starts, goals, args):
     return {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": upd / wall, "precision": "fp32"}
 
 
+def batch_scaling(n, T, sizes=(1, 16, 256), steps=30):
+    """Updates/s of the same step at fewer problems per launch (the single-problem rate
+    and partly filled GPUs), dense and structured, FP32, graph-replayed."""
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+    npairs = n * (n - 1) // 2
+    out = []
+    for solve in ("dense", "structured"):
+        plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, "fp32", solve=solve)
+        for B in sizes:
+            starts, goals = zip(*[sc.random_box(n, seed=q) for q in range(B)])
+            b = mato.Batch([plan] * B, starts, goals)
+            b.step(5)
+            b.sync()
+            t0 = time.perf_counter()
+            b.step(steps)
+            b.sync()
+            dt = (time.perf_counter() - t0) / steps
+            b.close()
+            out.append({"solve": solve, "problems": B, "ms_per_iter": dt * 1e3,
+                        "updates_per_s": npairs * T * B / dt})
+        plan.close()
+    return out
+
+
 def obstacle_scaling(n=16, counts=(0, 8, 16, 32, 64, 128), batch=256, iters=30):
     """Iteration time against the number of static obstacles (16 agents, T = 100): one
     problem alone and `batch` problems per launch; structured solve, FP32, graphs."""
@@ -354,6 +379,8 @@ def main():
     batch.close()
     if args.solve == "dense":
         out["structured_step"] = structured_step(n, T, B, starts, goals, args)
+    if not args.no_mixed:
+        out["batch_scaling"] = batch_scaling(n, T)
     if not args.no_serve:
         out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve,
