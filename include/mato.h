@@ -295,6 +295,12 @@ mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_max);
 mato_status mato_server_submit(mato_server s, int32_t n, const double* starts, const double* goals,
                                int64_t* id);
 
+/* As mato_server_submit, with n_obs static obstacles [n_obs][x, y, z, l_xy, l_z] (copied;
+ * plans are cached per agent count and obstacle count).  Errors as mato_server_submit and
+ * INVALID_ARG for n_obs outside 0..MATO_MAX_OBSTACLES or semi-axes not > 0. */
+mato_status mato_server_submit_ex(mato_server s, int32_t n, const double* starts, const double* goals,
+                                  int32_t n_obs, const double* obstacles, int64_t* id);
+
 /* One scheduling step: retire finished problems, admit queued ones, run `chunk`
  * iterations of the resident problems (asynchronously).  Reports resident and
  * queued counts after admission. */

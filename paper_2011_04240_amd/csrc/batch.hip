@@ -285,18 +285,21 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
                 for (int k = 0; k < P.nv; ++k) o[(size_t)a * P.ldc + (size_t)i * P.nv + k] = hc[((size_t)i * 3 + a) * P.nv + k];
         MATO_HIP(hipMemcpy(P.base + P.o_c, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice));
     }
-    S* dproj = nullptr;
-    WorkItem* ditems = nullptr;
-    ProblemDesc<S>* dd = nullptr;
-    MATO_HIP(hipMalloc(&dproj, sizeof(S) * proj_i.size()));
+    DevBuf<S> dprojb;
+    DevBuf<WorkItem> ditemsb;
+    DevBuf<ProblemDesc<S>> ddb;
+    MATO_TRY(dprojb.alloc(proj_i.size()));
+    S* dproj = dprojb.p;
     MATO_HIP(hipMemcpy(dproj, proj_i.data(), sizeof(S) * proj_i.size(), hipMemcpyHostToDevice));
     std::vector<WorkItem> items;
     for (const auto& w : B->hitems)
         if (w.prob == q) { WorkItem v = w; v.prob = 0; items.push_back(v); }
     ProblemDesc<S> D = B->hdesc[q];
     D.proj_in = dproj;
-    MATO_HIP(hipMalloc(&ditems, sizeof(WorkItem) * items.size()));
-    MATO_HIP(hipMalloc(&dd, sizeof(ProblemDesc<S>)));
+    MATO_TRY(ditemsb.alloc(items.size()));
+    MATO_TRY(ddb.alloc(1));
+    WorkItem* ditems = ditemsb.p;
+    ProblemDesc<S>* dd = ddb.p;
     MATO_HIP(hipMemcpy(ditems, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
     MATO_HIP(hipMemcpy(dd, &D, sizeof(D), hipMemcpyHostToDevice));
     int ctrl[kCtrl];
@@ -311,9 +314,6 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(hipStreamSynchronize(B->stream));
-    dfree(dproj);
-    dfree(ditems);
-    dfree(dd);
     return MATO_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -49,6 +50,30 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 inline void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
+
+// Device allocation with the library's error convention (OUT_OF_MEMORY, message set).
+template <typename T>
+inline mato_status dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (hipMalloc(p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("device allocation of %zu bytes failed", sizeof(T) * count);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
+    return MATO_OK;
+}
+
+// Scratch device buffer freed when it goes out of scope (every return path).
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { dfree(p); }
+    mato_status alloc(size_t count) { return dalloc(&p, count); }
+};
 
 // Pair p = (i, j), i < j, in the row order of A_fc: p(i, j) = i n - i(i+1)/2 + j - i - 1.
 __host__ __device__ inline int row_offset(int i, int n) { return i * n - i * (i + 1) / 2; }

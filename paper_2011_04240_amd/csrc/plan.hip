@@ -248,11 +248,14 @@ static int grid_for(size_t total, int block) {
 // inv[m].  Returns SINGULAR on a zero pivot; writes ||K||_1 ||K^{-1}||_1 to cond[m].
 static mato_status gauss_jordan(double* W, int N, int count, double* const* inv, double* cond, hipStream_t st) {
     const size_t ms = (size_t)N * 2 * N;
-    double *f = nullptr, *cs = nullptr;
-    int* flag = nullptr;
-    MATO_HIP(hipMalloc(&f, sizeof(double) * N * count));
-    MATO_HIP(hipMalloc(&cs, sizeof(double) * N * count));
-    MATO_HIP(hipMalloc(&flag, sizeof(int) * count));
+    DevBuf<double> fb, csb;
+    DevBuf<int> flagb;
+    MATO_TRY(fb.alloc((size_t)N * count));
+    MATO_TRY(csb.alloc((size_t)N * count));
+    MATO_TRY(flagb.alloc(count));
+    double* f = fb.p;
+    double* cs = csb.p;
+    int* flag = flagb.p;
     MATO_HIP(hipMemsetAsync(flag, 0, sizeof(int) * count, st));
     std::vector<double> h((size_t)N * count), norm1(count, 0.0);
     column_abs_sums<<<dim3((N + 255) / 256, count), 256, 0, st>>>(W, N, 0, ms, cs);
@@ -273,9 +276,6 @@ static mato_status gauss_jordan(double* W, int N, int count, double* const* inv,
     for (int m = 0; m < count; ++m)
         extract_inverse<<<grid_for((size_t)N * N, 256), 256, 0, st>>>(W + ms * m, N, inv[m]);
     MATO_HIP(hipStreamSynchronize(st));
-    dfree(f);
-    dfree(cs);
-    dfree(flag);
     mato_status status = MATO_OK;
     for (int m = 0; m < count; ++m) {
         double ninv = 0.0;
@@ -291,7 +291,7 @@ static mato_status gauss_jordan(double* W, int N, int count, double* const* inv,
 
 template <typename T>
 static mato_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
-    MATO_HIP(hipMalloc(dst, sizeof(T) * src.size()));
+    MATO_TRY(dalloc(dst, src.size()));
     MATO_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
     *bytes += sizeof(T) * src.size();
     return MATO_OK;
@@ -350,10 +350,11 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
             sig[2 * m + 1] = ps[m]->rho * n_obs;
             sig[2 * m + 2] = ps[m]->rho * (n + n_obs);
         }
-        double *W0 = nullptr, *inv0 = nullptr, *dsig = nullptr;
-        MATO_HIP(hipMalloc(&W0, sizeof(double) * ms0 * m0));
-        MATO_HIP(hipMalloc(&inv0, sizeof(double) * N0 * N0 * m0));
-        MATO_HIP(hipMalloc(&dsig, sizeof(double) * m0));
+        DevBuf<double> W0b, inv0b, dsigb;
+        MATO_TRY(W0b.alloc(ms0 * m0));
+        MATO_TRY(inv0b.alloc((size_t)N0 * N0 * m0));
+        MATO_TRY(dsigb.alloc(m0));
+        double *W0 = W0b.p, *inv0 = inv0b.p, *dsig = dsigb.p;
         MATO_HIP(hipMemcpy(dsig, sig.data(), sizeof(double) * m0, hipMemcpyHostToDevice));
         assemble_agent_kkt<<<dim3(1, m0), 256, 0, st>>>(W0, nv, nb, dsig, ms0, p0->dPtP, p0->dPddtPdd, p0->dA);
         std::vector<double*> invs(m0);
@@ -361,12 +362,8 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         std::vector<double> conds(m0, 0.0);
         mato_status s = gauss_jordan(W0, N0, m0, invs.data(), conds.data(), st);
         std::vector<double> h((size_t)N0 * N0 * m0);
-        if (s == MATO_OK)
-            MATO_HIP(hipMemcpy(h.data(), inv0, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
-        dfree(W0);
-        dfree(inv0);
-        dfree(dsig);
         if (s != MATO_OK) return s;
+        MATO_HIP(hipMemcpy(h.data(), inv0, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
         p0->K0inv_c.assign((size_t)nv * nb, 0.0);
         for (int r = 0; r < nv; ++r)
             for (int b = 0; b < nb; ++b) p0->K0inv_c[(size_t)r * nb + b] = h[(size_t)r * N0 + nv + b];
@@ -407,23 +404,19 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
     // KKT matrices of eq. (kkt_step_x), one per rho, inverted together
     const int N = n * (nv + nb), M = n * nv;
     const size_t ms = (size_t)N * 2 * N;
-    double* W = nullptr;
-    if (hipMalloc(&W, sizeof(double) * ms * cnt) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("device allocation of %zu bytes failed", sizeof(double) * ms * cnt);
-        return MATO_ERR_OUT_OF_MEMORY;
-    }
+    DevBuf<double> Wb;
+    MATO_TRY(Wb.alloc(ms * cnt));
+    double* W = Wb.p;
     std::vector<double*> invs(cnt);
     std::vector<double> conds(cnt, 0.0);
     for (int m = 0; m < cnt; ++m) {
-        MATO_HIP(hipMalloc(&ps[m]->dKinv, sizeof(double) * (size_t)N * N));
+        MATO_TRY(dalloc(&ps[m]->dKinv, (size_t)N * N));
         ps[m]->bytes += sizeof(double) * (size_t)N * N;
         invs[m] = ps[m]->dKinv;
         assemble_kkt<<<grid_for(ms, 256), 256, 0, st>>>(W + ms * m, n, n_obs, nv, nb, ps[m]->rho, ps[m]->dPtP,
                                                         ps[m]->dPddtPdd, ps[m]->dA);
     }
     mato_status s = gauss_jordan(W, N, cnt, invs.data(), conds.data(), st);
-    dfree(W);
     for (int m = 0; m < cnt; ++m) ps[m]->cond = conds[m];
     if (s != MATO_OK) return s;
 
@@ -438,10 +431,10 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
     if (p0->precision == MATO_FP64) { kind = 2; esz = sizeof(double); }
     for (auto p : ps) {
         p->ldk = ldk;
-        MATO_HIP(hipMalloc(&p->dAhi, esz * elems));
+        MATO_TRY(dalloc((char**)&p->dAhi, esz * elems));
         p->bytes += esz * elems;
         if (kind == 1) {
-            MATO_HIP(hipMalloc(&p->dAlo, esz * elems));
+            MATO_TRY(dalloc((char**)&p->dAlo, esz * elems));
             p->bytes += esz * elems;
         }
         extract_crows<<<grid_for(elems, 256), 256, 0, st>>>(p->dKinv, N, M, Mp, ldk, kind, p->dAhi, p->dAlo);

@@ -22,11 +22,12 @@ struct mato_server_s {
     mato_server_config cfg;
     hipStream_t stream = nullptr;
     void* eng = nullptr;                       // mato::Engine<float> or <double>
-    std::map<int, mato_plan> plans;            // per (agent count, rho stage): key n * kMaxStages + stage
+    std::map<int64_t, mato_plan> plans;        // per (agent count, obstacle count, rho stage): plan_key()
     struct Req {
         int64_t id = 0;
-        int n = 0;
+        int n = 0, n_obs = 0;
         std::vector<double> starts, goals, c;
+        std::vector<double> obstacles;         // [n_obs][5]
         int state = 0;                         // 0 queued, 1 running, 2 done
         int slot = -1;
         int iters = 0, converged = 0, nonfinite = 0;
@@ -44,6 +45,10 @@ struct mato_server_s {
 };
 
 namespace mato {
+
+static int64_t plan_key(int n, int n_obs, int stage) {
+    return ((int64_t)n * (MATO_MAX_OBSTACLES + 1) + n_obs) * kMaxStages + stage;
+}
 
 static size_t plan_bytes_estimate(int n, int nv, int T, int precision, int solve) {
     if (solve == MATO_SOLVE_STRUCTURED)
@@ -108,20 +113,21 @@ struct ServerOps {
         return false;
     }
 
-    // All stage plans of agent count n (created on demand, together, within the budget).
-    static mato_status get_plans(mato_server s, int n, std::vector<mato_plan>* out) {
+    // All stage plans of agent count n with n_obs obstacles (created on demand, together,
+    // within the budget).
+    static mato_status get_plans(mato_server s, int n, int n_obs, std::vector<mato_plan>* out) {
         out->clear();
         std::vector<int> missing;
         std::vector<double> rhos;
         for (int j = 0; j < stages(s); ++j)
-            if (!s->plans.count(n * kMaxStages + j)) {
+            if (!s->plans.count(plan_key(n, n_obs, j))) {
                 missing.push_back(j);
                 rhos.push_back(stage_rho(s, j));
             }
         if (!missing.empty()) {
             std::vector<mato_plan> keep;
             for (int j = 0; j < stages(s); ++j) {
-                auto it = s->plans.find(n * kMaxStages + j);
+                auto it = s->plans.find(plan_key(n, n_obs, j));
                 if (it != s->plans.end()) keep.push_back(it->second);
             }
             const size_t est = missing.size() * plan_bytes_estimate(n, s->cfg.basis.n_coef, s->cfg.T, s->cfg.precision,
@@ -129,12 +135,12 @@ struct ServerOps {
             if (!make_room(s, est, keep, -1)) return MATO_OK;     // not now: wait for memory
             std::vector<mato_plan> made(missing.size(), nullptr);
             mato_plan_desc d;
-            d.n = n; d.n_obs = 0; d.T = s->cfg.T; d.basis = s->cfg.basis; d.a = s->cfg.a; d.b = s->cfg.b;
+            d.n = n; d.n_obs = n_obs; d.T = s->cfg.T; d.basis = s->cfg.basis; d.a = s->cfg.a; d.b = s->cfg.b;
             d.precision = s->cfg.precision; d.solve = s->cfg.solve;
             MATO_TRY(mato_plan_create_ex(&d, rhos.data(), (int)rhos.size(), s->stream, made.data()));
-            for (size_t m = 0; m < missing.size(); ++m) s->plans[n * kMaxStages + missing[m]] = made[m];
+            for (size_t m = 0; m < missing.size(); ++m) s->plans[plan_key(n, n_obs, missing[m])] = made[m];
         }
-        for (int j = 0; j < stages(s); ++j) out->push_back(s->plans[n * kMaxStages + j]);
+        for (int j = 0; j < stages(s); ++j) out->push_back(s->plans[plan_key(n, n_obs, j)]);
         return MATO_OK;
     }
 
@@ -187,7 +193,7 @@ struct ServerOps {
         while (!s->queue.empty()) {
             auto& R = s->reqs[s->queue.front()];
             std::vector<mato_plan> sp;
-            MATO_TRY(get_plans(s, R.n, &sp));
+            MATO_TRY(get_plans(s, R.n, R.n_obs, &sp));
             if (sp.empty()) break;
             const mato_plan plan = sp[0];
             const size_t need = Engine<S>::slot_bytes(plan);
@@ -204,7 +210,8 @@ struct ServerOps {
             }
             e->probs[q].iter_cap = s->cfg.max_iters;
             e->probs[q].shifted = s->cfg.projection;
-            MATO_TRY(e->attach(q, plan, R.starts.data(), R.goals.data(), nullptr));
+            MATO_TRY(e->attach(q, plan, R.starts.data(), R.goals.data(), nullptr,
+                               R.n_obs > 0 ? R.obstacles.data() : nullptr));
             e->probs[q].stages.clear();
             e->probs[q].stage_start.clear();
             if (s->cfg.rho_stages > 0)
@@ -311,7 +318,7 @@ extern "C" mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_
     return sdispatch(s, [&](auto ops) -> mato_status {
         for (int n = std::max(2, (int)n_min); n <= n_max; ++n) {
             std::vector<mato_plan> p;
-            MATO_TRY(ops.get_plans(s, n, &p));
+            MATO_TRY(ops.get_plans(s, n, 0, &p));
             if (p.empty()) { set_error("device-memory budget too small to hold the plans for n = %d", n); return MATO_ERR_OUT_OF_MEMORY; }
         }
         return MATO_OK;
@@ -320,18 +327,30 @@ extern "C" mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_
 
 extern "C" mato_status mato_server_submit(mato_server s, int32_t n, const double* starts, const double* goals,
                                           int64_t* id) {
-    if (!s || !starts || !goals) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    return mato_server_submit_ex(s, n, starts, goals, 0, nullptr, id);
+}
+
+extern "C" mato_status mato_server_submit_ex(mato_server s, int32_t n, const double* starts, const double* goals,
+                                             int32_t n_obs, const double* obstacles, int64_t* id) {
+    if (!s || !starts || !goals || (n_obs > 0 && !obstacles)) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
     if (n < 2) { set_error("n = %d < 2", n); return MATO_ERR_INVALID_ARG; }
     if (n > MATO_MAX_AGENTS) { set_error("n = %d > %d", n, MATO_MAX_AGENTS); return MATO_ERR_UNSUPPORTED; }
+    if (n_obs < 0 || n_obs > MATO_MAX_OBSTACLES) {
+        set_error("n_obs = %d outside 0..%d", n_obs, MATO_MAX_OBSTACLES);
+        return MATO_ERR_INVALID_ARG;
+    }
     mato_server_s::Req R;
-    R.id = s->next_id++;
     R.n = n;
+    R.n_obs = n_obs;
     R.starts.resize((size_t)n * 3);
     R.goals.resize((size_t)n * 3);
+    R.obstacles.resize((size_t)n_obs * 5);
     if (hipMemcpy(R.starts.data(), starts, sizeof(double) * R.starts.size(), hipMemcpyDefault) != hipSuccess ||
-        hipMemcpy(R.goals.data(), goals, sizeof(double) * R.goals.size(), hipMemcpyDefault) != hipSuccess) {
+        hipMemcpy(R.goals.data(), goals, sizeof(double) * R.goals.size(), hipMemcpyDefault) != hipSuccess ||
+        (n_obs > 0 &&
+         hipMemcpy(R.obstacles.data(), obstacles, sizeof(double) * R.obstacles.size(), hipMemcpyDefault) != hipSuccess)) {
         (void)hipGetLastError();
-        set_error("cannot read starts/goals");
+        set_error("cannot read starts/goals/obstacles");
         return MATO_ERR_INVALID_ARG;
     }
     for (size_t k = 0; k < R.starts.size(); ++k)
@@ -339,6 +358,13 @@ extern "C" mato_status mato_server_submit(mato_server s, int32_t n, const double
             set_error("non-finite start or goal");
             return MATO_ERR_NONFINITE;
         }
+    for (int o = 0; o < n_obs; ++o) {
+        const double* ob = &R.obstacles[(size_t)5 * o];
+        for (int k = 0; k < 5; ++k)
+            if (!std::isfinite(ob[k])) { set_error("non-finite obstacle"); return MATO_ERR_NONFINITE; }
+        if (!(ob[3] > 0) || !(ob[4] > 0)) { set_error("obstacle semi-axes must be > 0"); return MATO_ERR_INVALID_ARG; }
+    }
+    R.id = s->next_id++;
     R.t_submit = s->now();
     s->queue.push_back(R.id);
     s->reqs[R.id] = std::move(R);

@@ -98,6 +98,7 @@ SIGNATURES = {
     "mato_server_destroy": (None, [_vp]),
     "mato_server_warm": (_i32, [_vp, _i32, _i32]),
     "mato_server_submit": (_i32, [_vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "mato_server_submit_ex": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "mato_server_step": (_i32, [_vp, _pi32, _pi32]),
     "mato_server_poll": (_i32, [_vp, ctypes.c_int64, _pi32, _pi32, _pi32, _pf64]),
     "mato_server_result": (_i32, [_vp, ctypes.c_int64, _vp]),
@@ -331,6 +332,13 @@ def mato_server_submit(server, n, starts, goals):
     return i.value
 
 
+def mato_server_submit_ex(server, n, starts, goals, n_obs, obstacles):
+    i = ctypes.c_int64()
+    _check(lib().mato_server_submit_ex(server, n, _ptr(starts), _ptr(goals), n_obs, _ptr(obstacles),
+                                       ctypes.byref(i)))
+    return i.value
+
+
 def mato_server_step(server):
     r, q = _i32(), _i32()
     _check(lib().mato_server_step(server, ctypes.byref(r), ctypes.byref(q)))
@@ -487,10 +495,14 @@ class Server:
     def warm(self, n_min, n_max):
         mato_server_warm(self.handle, n_min, n_max)
 
-    def submit(self, starts, goals):
+    def submit(self, starts, goals, obstacles=None):
+        """obstacles: optional [n_obs][x, y, z, l_xy, l_z] static obstacles of this request."""
         starts = np.ascontiguousarray(starts, np.float64)
         goals = np.ascontiguousarray(goals, np.float64)
-        return mato_server_submit(self.handle, starts.shape[0], starts, goals)
+        if obstacles is None or len(obstacles) == 0:
+            return mato_server_submit(self.handle, starts.shape[0], starts, goals)
+        obs = np.ascontiguousarray(np.asarray(obstacles, np.float64).reshape(-1, 5))
+        return mato_server_submit_ex(self.handle, starts.shape[0], starts, goals, obs.shape[0], obs)
 
     def step(self):
         return mato_server_step(self.handle)

@@ -142,3 +142,32 @@ def test_obstacle_errors():
     with pytest.raises(mato.MatoError) as e:
         mato.Batch([p], [s], [g], obstacles_list=[bad])
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
+
+
+def test_server_with_obstacles_alone_vs_mix():
+    """Requests with different obstacle counts (plans per agent and obstacle count) served
+    together finish exactly as each problem alone."""
+    say("server with obstacles")
+    cases = [(6, 4, 1), (9, 0, 2), (5, 7, 3), (9, 4, 4)]
+    scen = [sc.obstacle_box(n, k, seed=sd) for n, k, sd in cases]
+    srv = mato.Server(T=50, t_final=5.0, a=0.3, b=0.6, precision="fp32", max_slots=2, chunk=5, max_iters=300,
+                      tol=1e-3, solve="structured")
+    ids = [srv.submit(s, g, o) for s, g, o in scen]
+    out = {}
+    for _ in range(100000):
+        srv.step()
+        for k, i in enumerate(ids):
+            if k not in out and srv.poll(i)[0] == 2:
+                st, it, conv, _ = srv.poll(i)
+                out[k] = (srv.result(i, cases[k][0]), it, conv)
+        if len(out) == len(ids):
+            break
+    assert len(out) == len(ids)
+    for k, (n, n_obs, _) in enumerate(cases):
+        p = _gplan("fp32", "structured", n_obs, n, 50, 5.0)
+        b = mato.Batch([p], [scen[k][0]], [scen[k][1]], obstacles_list=[scen[k][2]])
+        b.run(300, 1e-3, 5)
+        it, conv = b.status(0)
+        c, its, convs = out[k]
+        assert its == it and convs == conv
+        np.testing.assert_array_equal(c, b.coeffs(0))
