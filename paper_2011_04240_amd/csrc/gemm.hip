@@ -30,6 +30,18 @@ __device__ inline unsigned short f2bf_rne(float x) {
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (blockIdx mod 8), each XCD with
+// its own L2.  The tile list holds the 64-row tiles of one 64-column block consecutively,
+// so workgroup b takes tile start(b mod 8) + b / 8: each XCD gets a contiguous run of
+// tiles and the right-hand sides of a column block are fetched into one L2 instead of
+// eight.  A bijection for any tile count.
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int b, int ntiles) {
+    const int q = ntiles / kXcds, r = ntiles % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + min(x, r) + j;
+}
+
 struct TileCols {
     const double* bptr;
     const float* bfptr;
@@ -115,7 +127,7 @@ __device__ inline void finish_tile(const GemmTile& t, const GemmGroup& G, const 
 __global__ __launch_bounds__(512) void gemm_f32(const GemmTile* __restrict__ tiles,
                                                 const GemmGroup* __restrict__ groups,
                                                 const GemmCol* __restrict__ cols, int accumulate) {
-    const GemmTile t = tiles[blockIdx.x];
+    const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
     constexpr int LD = 80;                      // row stride: conflict-free MFMA operand reads
     __shared__ float smem[2 * 2 * 32 * LD];     // per group: A [k][m], B [k][rhs]
@@ -197,7 +209,7 @@ __device__ inline void split8(const float4& x0, const float4& x1, ushortx8& hi, 
 __global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ tiles,
                                                  const GemmGroup* __restrict__ groups,
                                                  const GemmCol* __restrict__ cols, int accumulate) {
-    const GemmTile t = tiles[blockIdx.x];
+    const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
     constexpr int LDH = 40;                                   // [row][k] stride in bf16 elements
     __shared__ __align__(16) unsigned short smem[2 * 4 * 64 * LDH];
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ ti
 __global__ __launch_bounds__(256) void gemm_f64(const GemmTile* __restrict__ tiles,
                                                 const GemmGroup* __restrict__ groups,
                                                 const GemmCol* __restrict__ cols, int accumulate) {
-    const GemmTile t = tiles[blockIdx.x];
+    const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
     __shared__ double As[16][65];   // [k][m]
     __shared__ double Bs[16][65];   // [k][rhs]
