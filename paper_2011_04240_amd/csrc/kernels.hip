@@ -330,22 +330,23 @@ template <typename S, int NV>
 __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
     const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldc = Dp->ldc;
     gptr<const double> Pm = glob(Dp->P);
-    gptr<const double> Pddm = glob(Dp->Pdd);
+    gptr<const double> Gm = glob(Dp->PddtPdd);
     gptr<const double> cm = glob((const double*)Dp->c);
     gptr<S> Xm = glob(Dp->X);
-    constexpr int kRows = 1536;                    // basis entries staged per chunk (12 KB each)
-    __shared__ double Ps[kRows], Pdds[kRows];
+    constexpr int kRows = 3072;                    // basis entries staged per chunk (24 KB)
+    __shared__ double Ps[kRows];
+    __shared__ double G[kMaxCoef * kMaxCoef];      // Pddot^T Pddot
     __shared__ double red[3 * 4];
     const int n3 = 3 * n;
-    const int TC = kRows / nv;                     // instants per chunk (139 for 11 coefficients)
+    const int TC = kRows / nv;                     // instants per chunk (279 for 11 coefficients)
+    for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) G[e] = Gm[e];
+    // The smoothness cost sum_t (Pddot c)^2 of a column is the quadratic form
+    // c^T (Pddot^T Pddot) c: n_v^2 products per column instead of T n_v.
     double cost = 0.0;
     for (int tb = 0; tb < T; tb += TC) {
         const int tn = min(TC, T - tb);
         __syncthreads();
-        for (int e = threadIdx.x; e < tn * nv; e += blockDim.x) {
-            Ps[e] = Pm[(size_t)tb * nv + e];
-            Pdds[e] = Pddm[(size_t)tb * nv + e];
-        }
+        for (int e = threadIdx.x; e < tn * nv; e += blockDim.x) Ps[e] = Pm[(size_t)tb * nv + e];
         __syncthreads();
         for (int col = threadIdx.x; col < n3; col += blockDim.x) {
             const int a = col / n, i = col - a * n;
@@ -354,43 +355,44 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
                 double cv[NV];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) cv[k] = ci[k];
+                if (tb == 0) {
+#pragma unroll 1
+                    for (int k = 0; k < NV; ++k) {
+                        double gk = 0.0;
+#pragma unroll
+                        for (int l = 0; l < NV; ++l) gk += G[k * NV + l] * cv[l];
+                        cost += ci[k] * gk;          // ci[k] == cv[k], read from memory (k not unrolled)
+                    }
+                }
                 int t = 0;
-                // four instants at a time: eight independent FMA chains and their LDS
-                // reads in flight together (same k and t order as one at a time)
+                // four instants at a time: four independent FMA chains and their LDS reads
+                // in flight together
                 for (; t + 4 <= tn; t += 4) {
-                    double x[4] = {0.0, 0.0, 0.0, 0.0}, acc[4] = {0.0, 0.0, 0.0, 0.0};
+                    double x[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int k = 0; k < NV; ++k)
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            x[u] += Ps[(t + u) * NV + k] * cv[k];
-                            acc[u] += Pdds[(t + u) * NV + k] * cv[k];
-                        }
+                        for (int u = 0; u < 4; ++u) x[u] += Ps[(t + u) * NV + k] * cv[k];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        Xm[(size_t)(tb + t + u) * n3 + col] = (S)x[u];
-                        cost += acc[u] * acc[u];
-                    }
+                    for (int u = 0; u < 4; ++u) Xm[(size_t)(tb + t + u) * n3 + col] = (S)x[u];
                 }
                 for (; t < tn; ++t) {
-                    double x = 0.0, acc = 0.0;
+                    double x = 0.0;
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) {
-                        x += Ps[t * NV + k] * cv[k];
-                        acc += Pdds[t * NV + k] * cv[k];
-                    }
+                    for (int k = 0; k < NV; ++k) x += Ps[t * NV + k] * cv[k];
                     Xm[(size_t)(tb + t) * n3 + col] = (S)x;
-                    cost += acc * acc;
                 }
             } else {
-                for (int t = 0; t < tn; ++t) {
-                    double x = 0.0, acc = 0.0;
+                if (tb == 0)
                     for (int k = 0; k < nv; ++k) {
-                        x += Ps[t * nv + k] * ci[k];
-                        acc += Pdds[t * nv + k] * ci[k];
+                        double gk = 0.0;
+                        for (int l = 0; l < nv; ++l) gk += G[k * nv + l] * ci[l];
+                        cost += ci[k] * gk;
                     }
+                for (int t = 0; t < tn; ++t) {
+                    double x = 0.0;
+                    for (int k = 0; k < nv; ++k) x += Ps[t * nv + k] * ci[k];
                     Xm[(size_t)(tb + t) * n3 + col] = (S)x;
-                    cost += acc * acc;
                 }
             }
         }
