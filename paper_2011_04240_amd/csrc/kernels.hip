@@ -518,15 +518,27 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
                 if (col >= n3) continue;
                 gptr<const S> sp = ss + (size_t)tb * n3 + col;     // [(t*3 + a)*n + i] = t*3n + col
                 int t = 0;
-                for (; t + 8 <= tn; t += 8) {
-                    S sv[8];
+                // 8 instants per step, the next 8 loaded while these are multiplied out
+                S sv[8], sn[8];
+                if (tn >= 8) {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) sv[u] = sp[(size_t)(t + u) * n3];
+                    for (int u = 0; u < 8; ++u) sv[u] = sp[(size_t)u * n3];
+                }
+                for (; t + 8 <= tn; t += 8) {
+                    const bool more = t + 16 <= tn;
+                    if (more) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sn[u] = sp[(size_t)(t + 8 + u) * n3];
+                    }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const double su = (double)sv[u];
 #pragma unroll
                         for (int k = 0; k < NV; ++k) acc[h][k] += Ps[(t + u) * NV + k] * su;
+                    }
+                    if (more) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sv[u] = sn[u];
                     }
                 }
                 for (; t < tn; ++t) {
