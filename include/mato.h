@@ -344,6 +344,15 @@ mato_status mato_get_state(mato_solve s, void* c, void* lambda, void* proj, void
 mato_status mato_set_state(mato_solve s, const void* c, const void* lambda, const void* proj);
 void        mato_solve_destroy(mato_solve s);
 
+/* --------------------------------------------------------------- streams ---
+ * A HIP stream of the library's own runtime (non-blocking, default priority), for
+ * callers that advance several batches concurrently: each batch enqueues its work on
+ * the stream given at its creation, so batches on different streams overlap on the
+ * device (one's pairwise stage, bound by HBM, beside another's per-problem kernels).
+ * Destroy a stream only after the batches using it. */
+mato_status mato_stream_create(void** out);
+mato_status mato_stream_destroy(void* stream);
+
 /* ---------------------------------------------------------- measurement ---
  * Not part of the method: allocates two device buffers of `bytes` (a positive multiple
  * of 16), fills the source, and times `iters` launches (after one warm-up) of a

@@ -457,3 +457,18 @@ extern "C" mato_status mato_set_state(mato_solve s, const void* c, const void* l
 }
 
 extern "C" void mato_solve_destroy(mato_solve s) { mato_batch_destroy(s); }
+
+extern "C" mato_status mato_stream_create(void** out) {
+    if (!out) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    *out = nullptr;
+    hipStream_t st = nullptr;
+    MATO_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
+    *out = st;
+    return MATO_OK;
+}
+
+extern "C" mato_status mato_stream_destroy(void* stream) {
+    if (!stream) { set_error("null stream"); return MATO_ERR_INVALID_ARG; }
+    MATO_HIP(hipStreamDestroy((hipStream_t)stream));
+    return MATO_OK;
+}

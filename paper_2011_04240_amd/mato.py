@@ -113,6 +113,8 @@ SIGNATURES = {
     "mato_get_state": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
     "mato_stream_copy": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
+    "mato_stream_create": (_i32, [_pvp]),
+    "mato_stream_destroy": (_i32, [_vp]),
 }
 
 
@@ -154,9 +156,31 @@ def _ptr(x):
 def _stream_ptr(stream):
     if stream is None:
         return None
+    if isinstance(stream, Stream):
+        return stream.handle
     if hasattr(stream, "cuda_stream"):
         return ctypes.c_void_p(stream.cuda_stream)
     return ctypes.c_void_p(int(stream))
+
+
+class Stream:
+    """A HIP stream created by the library's runtime (batches on different streams overlap)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().mato_stream_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mato_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --------------------------------------------------------- thin C wrappers ---
