@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--serve-solve", default="structured", choices=["dense", "structured"])
     ap.add_argument("--sweep-requests", type=int, default=2000,
                     help="requests per rate in the sweep (fewer where the trace would exceed 90 s)")
+    ap.add_argument("--serve-chunk", type=int, default=10, help="iterations per server scheduling step")
     ap.add_argument("--serve-graphs", action="store_true",
                     help="replay the server's iterations from HIP graphs (recaptured when the resident set changes)")
     ap.add_argument("--serve-fixed-rho", action="store_true",
@@ -356,8 +357,8 @@ def main():
         sweep = []
         for k, r in enumerate([10, 20, 50, 100, 200, 500]):
             sweep.append(serve_trace(r, min(args.sweep_requests, int(r * 90)), args.serve_precision, seed=k,
-                                     schedule=not args.serve_fixed_rho, solve=args.serve_solve,
-                                     use_graphs=args.serve_graphs))
+                                     chunk=args.serve_chunk, schedule=not args.serve_fixed_rho,
+                                     solve=args.serve_solve, use_graphs=args.serve_graphs))
             print(f"rate {r}/s: p50 {sweep[-1]['p50_ms']:.1f} ms, p99 {sweep[-1]['p99_ms']:.1f} ms",
                   file=sys.stderr, flush=True)
         print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
@@ -435,8 +436,8 @@ def main():
         out["batch_scaling"] = batch_scaling(n, T)
     if not args.no_serve:
         out["served"] = serve_trace(args.serve_rate, args.serve_requests, args.serve_precision,
-                                    schedule=not args.serve_fixed_rho, solve=args.serve_solve,
-                                    use_graphs=args.serve_graphs)
+                                    chunk=args.serve_chunk, schedule=not args.serve_fixed_rho,
+                                    solve=args.serve_solve, use_graphs=args.serve_graphs)
     if not args.no_mixed:
         out["mixed_batching"] = mixed_batching()
     if not args.no_obstacles:

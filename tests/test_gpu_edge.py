@@ -236,3 +236,28 @@ def test_stream_copy_probe():
     with pytest.raises(mato.MatoError) as e:
         mato.mato_stream_copy(15, 256, 1)
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
+
+
+def test_batches_on_library_streams():
+    """Two batches on their own library streams, stepped together, give exactly the
+    iterates of the same problems in one batch on the default stream."""
+    say("library streams")
+    ns = [7, 12, 9]
+    scen = [sc.random_density_box(n, seed=90 + k) for k, n in enumerate(ns)]
+    plans = [mato.Plan(n, 40, 11, 4.0, 0.3, 0.6, 1.0, "fp32") for n in ns]
+    ref = mato.Batch(plans, [x[0] for x in scen], [x[1] for x in scen])
+    ref.step(25)
+    s1, s2 = mato.Stream(), mato.Stream()
+    b1 = mato.Batch(plans[:2], [x[0] for x in scen[:2]], [x[1] for x in scen[:2]], stream=s1)
+    b2 = mato.Batch(plans[2:], [x[0] for x in scen[2:]], [x[1] for x in scen[2:]], stream=s2)
+    b1.step(25)
+    b2.step(25)
+    b1.sync()
+    b2.sync()
+    for q in range(2):
+        np.testing.assert_array_equal(b1.coeffs(q), ref.coeffs(q))
+    np.testing.assert_array_equal(b2.coeffs(0), ref.coeffs(2))
+    b1.close()
+    b2.close()
+    s1.close()
+    s2.close()
