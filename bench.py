@@ -242,6 +242,41 @@ def batch_scaling(n, T, sizes=(1, 16, 256), steps=30):
     return out
 
 
+def solve_times(ns=(8, 16, 32), seeds=4):
+    """Wall time of whole solves of one problem (batch creation, initialisation and the
+    iterations until max ||f_c|| < 1e-3 m, cap 2000; plans built beforehand, as the paper
+    builds its inverses offline): n agents swapping across a circle (radius max(2, n/(2 pi)) m,
+    neighbours about 1 m apart) and random-box problems at the n = 64 density, ten increasing
+    rho, dense and structured x/y/z step, FP32."""
+    from paper_2011_04240_amd import mato
+    from paper_2011_04240_amd import scenarios as sc
+    rhos, starts_it = RHO_SCHEDULE
+    out = []
+    for solve in ("dense", "structured"):
+        for n in ns:
+            plans = mato.Plan.schedule(n, 100, rhos, 11, 10.0, 0.3, 0.6, "fp32", solve=solve)
+            for kind in ("swap", "box"):
+                times, iters = [], []
+                for seed in range(seeds):
+                    if kind == "swap":
+                        s, g = sc.swap_circle(n, radius=max(2.0, 0.5 * n / np.pi), seed=seed)
+                    else:
+                        s, g = sc.random_density_box(n, seed=seed)
+                    t0 = time.perf_counter()
+                    b = mato.Batch([plans[0]], [s], [g])
+                    b.set_rho_schedule([[p] for p in plans], starts_it)
+                    b.run(2000, 1e-3, 10)
+                    it, conv = b.status(0)
+                    times.append(time.perf_counter() - t0)
+                    iters.append(it)
+                    b.close()
+                out.append({"solve": solve, "n": n, "scenario": kind, "ms_median": float(np.median(times) * 1e3),
+                            "iterations_median": float(np.median(iters))})
+            for p in plans:
+                p.close()
+    return out
+
+
 def obstacle_scaling(n=16, counts=(0, 8, 16, 32, 64, 128), batch=256, iters=30):
     """Iteration time against the number of static obstacles (16 agents, T = 100): one
     problem alone and `batch` problems per launch; structured solve, FP32, graphs."""
@@ -442,6 +477,8 @@ def main():
         out["mixed_batching"] = mixed_batching()
     if not args.no_obstacles:
         out["obstacle_scaling"] = obstacle_scaling()
+    if not args.no_mixed:
+        out["solve_times"] = solve_times()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds)
     print(json.dumps(out))
