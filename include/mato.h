@@ -303,16 +303,20 @@ mato_status mato_server_submit_ex(mato_server s, int32_t n, const double* starts
 
 /* One scheduling step: retire finished problems, admit queued ones, run `chunk`
  * iterations of the resident problems (asynchronously).  Reports resident and
- * queued counts after admission. */
+ * queued counts after admission.  A request that can never run is rejected here
+ * instead of holding up the queue: its plan could not be built, or with nothing
+ * resident the budget still cannot hold its plans and state. */
 mato_status mato_server_step(mato_server s, int32_t* running, int32_t* queued);
 
-/* state: 0 queued, 1 resident, 2 finished; iterations taken, converged flag, last
- * max ||f_c||.  NOT_FOUND for unknown (or already collected) ids. */
+/* state: 0 queued, 1 resident, 2 finished, 3 rejected; iterations taken, converged
+ * flag, last max ||f_c||.  NOT_FOUND for unknown (or already collected) ids. */
 mato_status mato_server_poll(mato_server s, int64_t id, int32_t* state, int32_t* iters,
                              int32_t* converged, double* r_max);
 
 /* Coefficients [n][3][n_coef] of a finished problem; forgets the request.
- * NONFINITE if its iteration produced non-finite values. */
+ * NONFINITE if its iteration produced non-finite values.  For a rejected request it
+ * writes nothing, forgets the request and returns the reason (OUT_OF_MEMORY, or the
+ * status of the failed plan build). */
 mato_status mato_server_result(mato_server s, int64_t id, double* c);
 
 mato_status mato_server_stats(mato_server s, double* device_bytes, int32_t* n_plans,
@@ -322,7 +326,7 @@ mato_status mato_server_stats(mato_server s, double* device_bytes, int32_t* n_pl
  * concatenated as [request][agent][3]) arrives arrival_s[k] seconds after the call
  * (non-decreasing).  Writes each request's latency (finish - arrival, seconds), its
  * iterations and convergence flag, and the wall time of the whole trace; results
- * are not kept. */
+ * are not kept.  A rejected request reports 0 iterations and converged 0. */
 mato_status mato_server_run_trace(mato_server s, int32_t count, const double* arrival_s,
                                   const int32_t* n, const double* starts, const double* goals,
                                   double* latency_s, int32_t* iters, int32_t* converged,

@@ -111,6 +111,7 @@ struct Engine {
     ProblemDesc<S>* ddesc = nullptr;
     double** dk0c = nullptr;
     double** dkinv = nullptr;
+    std::vector<double*> hk0c, hkinv;        // host copies: the source of every upload of a slot's pointers
 
     std::vector<WorkItem> hitems;
     WorkItem* ditems = nullptr;
@@ -228,6 +229,8 @@ struct Engine {
     mato_status init_capacity(int cap) {
         probs.resize(cap);
         hdesc.assign(cap, ProblemDesc<S>());
+        hk0c.assign(cap, nullptr);
+        hkinv.assign(cap, nullptr);
         MATO_HIP(hipMalloc(&dctrl, sizeof(int) * kCtrl * cap));
         MATO_HIP(hipMemset(dctrl, 0, sizeof(int) * kCtrl * cap));
         MATO_HIP(hipMalloc(&ddesc, sizeof(ProblemDesc<S>) * cap));
@@ -455,10 +458,10 @@ struct Engine {
                 return MATO_ERR_NONFINITE;
             }
         P.active = true;
-        double* k0 = plan->dK0c;
-        double* ki = plan->dKinv;
-        MATO_HIP(hipMemcpyAsync(dk0c + q, &k0, sizeof(double*), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipMemcpyAsync(dkinv + q, &ki, sizeof(double*), hipMemcpyHostToDevice, stream));
+        hk0c[q] = plan->dK0c;
+        hkinv[q] = plan->dKinv;
+        MATO_HIP(hipMemcpyAsync(dk0c + q, &hk0c[q], sizeof(double*), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
         MATO_HIP(hipStreamSynchronize(stream));
         lists_dirty = true;
         return MATO_OK;
@@ -664,8 +667,8 @@ struct Engine {
             if (P.iters_host != P.stage_start[P.stage + 1]) continue;
             P.stage += 1;
             P.plan = P.stages[P.stage];
-            double* ki = P.plan->dKinv;
-            MATO_HIP(hipMemcpyAsync(dkinv + q, &ki, sizeof(double*), hipMemcpyHostToDevice, stream));
+            hkinv[q] = P.plan->dKinv;
+            MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
             moved.push_back(q);
         }
         if (moved.empty()) return MATO_OK;

@@ -12,6 +12,7 @@
 // `chunk` iterations of all resident problems.
 #include <chrono>
 #include <deque>
+#include <string>
 #include <thread>
 
 #include "engine.h"
@@ -28,7 +29,9 @@ struct mato_server_s {
         int n = 0, n_obs = 0;
         std::vector<double> starts, goals, c;
         std::vector<double> obstacles;         // [n_obs][5]
-        int state = 0;                         // 0 queued, 1 running, 2 done
+        int state = 0;                         // 0 queued, 1 running, 2 done, 3 rejected
+        mato_status fail = MATO_OK;            // why a rejected request could not run
+        std::string why;
         int slot = -1;
         int iters = 0, converged = 0, nonfinite = 0;
         double r_max = 0.0;
@@ -187,14 +190,34 @@ struct ServerOps {
         return MATO_OK;
     }
 
+    // The request at the head of the queue cannot run at all: it leaves the queue as
+    // finished-with-failure so that the requests behind it are not held up.
+    static void reject(mato_server s, mato_status st, const char* why) {
+        auto& R = s->reqs[s->queue.front()];
+        R.state = 3;
+        R.fail = st;
+        R.why = why;
+        R.t_done = s->now();
+        s->finished.push_back(R.id);
+        s->queue.pop_front();
+    }
+
     static mato_status admit(mato_server s) {
         Engine<S>* e = E(s);
         std::vector<int> admitted;
         while (!s->queue.empty()) {
             auto& R = s->reqs[s->queue.front()];
             std::vector<mato_plan> sp;
-            MATO_TRY(get_plans(s, R.n, R.n_obs, &sp));
-            if (sp.empty()) break;
+            const mato_status pst = get_plans(s, R.n, R.n_obs, &sp);
+            if (pst != MATO_OK) { reject(s, pst, last_error()); continue; }
+            if (sp.empty()) {
+                // with nothing resident every evictable byte was already freed: it never fits
+                if (e->active_count() == 0) {
+                    reject(s, MATO_ERR_OUT_OF_MEMORY, "the device-memory budget cannot hold the plans of this request");
+                    continue;
+                }
+                break;
+            }
             const mato_plan plan = sp[0];
             const size_t need = Engine<S>::slot_bytes(plan);
             int q = -1;
@@ -206,7 +229,14 @@ struct ServerOps {
             const bool reuse = e->probs[q].own && e->probs[q].block >= need;
             if (!reuse) {
                 e->release_block(q);
-                if (!make_room(s, need, sp, q)) break;
+                if (!make_room(s, need, sp, q)) {
+                    if (e->active_count() == 0) {
+                        reject(s, MATO_ERR_OUT_OF_MEMORY,
+                               "the device-memory budget cannot hold this request's plans and state together");
+                        continue;
+                    }
+                    break;
+                }
             }
             e->probs[q].iter_cap = s->cfg.max_iters;
             e->probs[q].shifted = s->cfg.projection;
@@ -392,6 +422,12 @@ extern "C" mato_status mato_server_result(mato_server s, int64_t id, double* c) 
     if (!s || !c) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) { set_error("unknown request %lld", (long long)id); return MATO_ERR_NOT_FOUND; }
+    if (it->second.state == 3) {
+        const mato_status st = it->second.fail;
+        set_error("request %lld was rejected: %s", (long long)id, it->second.why.c_str());
+        s->reqs.erase(it);
+        return st;
+    }
     if (it->second.state != 2) { set_error("request %lld is not finished", (long long)id); return MATO_ERR_INVALID_ARG; }
     if (hipMemcpy(c, it->second.c.data(), sizeof(double) * it->second.c.size(), hipMemcpyDefault) != hipSuccess) {
         (void)hipGetLastError();

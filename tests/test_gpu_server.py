@@ -125,3 +125,38 @@ def test_server_errors():
     with pytest.raises(mato.MatoError) as e:
         srv.submit(s, g)
     assert e.value.status == mato.MATO_ERR_NONFINITE
+
+
+def test_request_that_never_fits_is_rejected():
+    say("server rejects a request the budget can never hold")
+    s40, g40 = sc.random_density_box(40, seed=501)
+    s10, g10 = sc.random_density_box(10, seed=502)
+    budget = 2.3e6      # holds the n = 10 plan and a slot, never the n = 40 plan (about 4.5 MB)
+    srv = mato.Server(T=T, t_final=TF, a=A, b=B, precision="fp32", max_slots=2, chunk=5, max_iters=300,
+                      tol=1e-3, hbm_budget_bytes=budget)
+    big = srv.submit(s40, g40)
+    small = srv.submit(s10, g10)
+    srv.step()
+    st, it, conv, _ = srv.poll(big)
+    assert st == 3 and it == 0 and conv == 0
+    with pytest.raises(mato.MatoError) as e:
+        srv.result(big, 40)
+    assert e.value.status == mato.MATO_ERR_OUT_OF_MEMORY
+    with pytest.raises(mato.MatoError) as e:
+        srv.poll(big)           # forgotten once collected
+    assert e.value.status == mato.MATO_ERR_NOT_FOUND
+    out = _drain(srv, [small], [10])
+    c, it, conv = _alone(10, s10, g10, "fp32", 1e-3, 300)
+    assert out[0][1] == it and out[0][2] == conv
+    np.testing.assert_array_equal(out[0][0], c)
+
+
+def test_trace_with_a_rejected_request_ends():
+    say("server trace with a rejected request")
+    ns = [8, 40, 8]
+    scen = [sc.random_density_box(n, seed=600 + k) for k, n in enumerate(ns)]
+    srv = mato.Server(T=T, t_final=TF, a=A, b=B, precision="fp32", max_slots=2, chunk=5, max_iters=300,
+                      tol=1e-3, hbm_budget_bytes=2.3e6)
+    lat, its, conv, wall = srv.run_trace([0.0, 0.001, 0.002], [x[0] for x in scen], [x[1] for x in scen])
+    assert its[1] == 0 and conv[1] == 0
+    assert its[0] > 0 and its[2] > 0 and conv[0] == 1 and conv[2] == 1
