@@ -353,18 +353,20 @@ def mixed_batching(count=256, iters=30, seed=0):
             "speedup": t_solo / t_batch}
 
 
-def stream_ceiling(nbytes):
-    """Best rate of the library's streaming copy (equal HBM reads and writes) over a few
-    grid sizes, for `nbytes` each way: the practical ceiling of the multiplier stream."""
+def stream_ceiling(nbytes, probe="copy"):
+    """Best rate of the library's streaming copy, or of its in-place streaming update (equal
+    HBM reads and writes, at the same addresses: the multipliers' pattern), over a few grid
+    sizes, for `nbytes` each way: the practical ceilings of the multiplier stream."""
     from paper_2011_04240_amd import mato
+    fn = mato.mato_stream_copy if probe == "copy" else mato.mato_stream_update
     nbytes -= nbytes % 16
     best = None
     for grid in (1024, 2048, 4096, 16384, 65536):
-        ms = mato.mato_stream_copy(nbytes, grid, 10)
+        ms = fn(nbytes, grid, 10)
         gbs = 2 * nbytes / (ms * 1e-3) / 1e9
         if best is None or gbs > best[0]:
             best = (gbs, grid, ms)
-    return {"GBps": best[0], "grid": best[1], "ms_per_copy": best[2], "bytes_each_way": nbytes}
+    return {"GBps": best[0], "grid": best[1], "ms_per_pass": best[2], "bytes_each_way": nbytes}
 
 
 def copy_calibration(mib):
@@ -430,6 +432,7 @@ def main():
     traffic = traffic_from_counters() if (n, T, B) == (64, 100, 1024) else None
     batch.timing(False)
     stream = stream_ceiling(alg_bytes // 2)
+    stream_upd = stream_ceiling(alg_bytes // 2, "update")
     r_max, _, _ = batch.residuals(0)
     batch.close()
     single = {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": value}
@@ -461,7 +464,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "stream_copy": stream, "frac_of_stream_copy": achieved / stream["GBps"]},
+                     "stream_copy": stream, "frac_of_stream_copy": achieved / stream["GBps"],
+                     "stream_update": stream_upd, "frac_of_stream_update": achieved / stream_upd["GBps"]},
         "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
         "single_stream": single,
     }

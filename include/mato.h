@@ -367,6 +367,13 @@ mato_status mato_stream_destroy(void* stream);
  * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (also if the copy differs). */
 mato_status mato_stream_copy(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream, double* ms_per_copy);
 
+/* Not part of the method: as mato_stream_copy for one buffer of `bytes` updated in
+ * place (x <- x/2 + 1, 16-byte nontemporal loads and stores): the access pattern of the
+ * multipliers, read and written back at the same addresses.  Checks the first and last
+ * 64 KiB against the value the recurrence gives on the host.  Writes the mean time of
+ * one pass.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (also on a wrong value). */
+mato_status mato_stream_update(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream, double* ms_per_update);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,7 +1,8 @@
-// Measurement utility of libmato: a streaming copy kernel (equal HBM reads and writes,
-// 16-byte nontemporal accesses, grid-stride), the practical ceiling against which the
-// pairwise stage's multiplier stream (12 bytes read and 12 written per pair-instant)
-// is compared.  Not part of the method.
+// Measurement utilities of libmato: a streaming copy and a streaming in-place update
+// (equal HBM reads and writes, 16-byte nontemporal accesses, grid-stride), the
+// practical ceilings against which the pairwise stage's multiplier stream (12 bytes
+// read and 12 written back in place per pair-instant) is compared.  Not part of the
+// method.
 #include "common.h"
 
 #include <algorithm>
@@ -14,6 +15,13 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(const v4f* __restrict_
                                                           size_t n4) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// x <- x / 2 + 1 in place (x / 2 is exact, so the value after k launches is the same
+// on the host in FP32)
+__global__ __launch_bounds__(256) void stream_update_kernel(v4f* __restrict__ x, size_t n4) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) * 0.5f + 1.0f, x + i);
 }
 
 }  // namespace mato
@@ -65,5 +73,52 @@ extern "C" mato_status mato_stream_copy(int64_t bytes, int32_t grid, int32_t ite
     dfree(src);
     dfree(dst);
     if (status == MATO_OK) *ms_per_copy = (double)ms / iters;
+    return status;
+}
+
+extern "C" mato_status mato_stream_update(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream,
+                                          double* ms_per_update) {
+    if (!ms_per_update || bytes < 16 || bytes % 16 != 0 || grid < 1 || iters < 1) {
+        set_error("stream update: bytes a positive multiple of 16, grid and iters >= 1");
+        return MATO_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t n4 = (size_t)bytes / 16;
+    void* x = nullptr;
+    if (hipMalloc(&x, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %lld bytes failed", (long long)bytes);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.0f;
+    std::vector<float> head(std::min<size_t>((size_t)bytes, 65536) / 4), tail(head.size());
+    auto run = [&]() -> mato_status {
+        MATO_HIP(hipMemsetAsync(x, 0, (size_t)bytes, st));
+        MATO_HIP(hipEventCreate(&e0));
+        MATO_HIP(hipEventCreate(&e1));
+        stream_update_kernel<<<grid, 256, 0, st>>>((v4f*)x, n4);                      // warm-up
+        MATO_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < iters; ++r) stream_update_kernel<<<grid, 256, 0, st>>>((v4f*)x, n4);
+        MATO_HIP(hipEventRecord(e1, st));
+        MATO_HIP(hipEventSynchronize(e1));
+        MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
+        MATO_HIP(hipMemcpy(head.data(), x, head.size() * 4, hipMemcpyDeviceToHost));
+        MATO_HIP(hipMemcpy(tail.data(), (char*)x + (bytes - (int64_t)tail.size() * 4), tail.size() * 4,
+                           hipMemcpyDeviceToHost));
+        float want = 0.0f;
+        for (int r = 0; r <= iters; ++r) want = want * 0.5f + 1.0f;
+        for (size_t k = 0; k < head.size(); ++k)
+            if (head[k] != want || tail[k] != want) {
+                set_error("stream update: unexpected value after %d launches", iters + 1);
+                return MATO_ERR_HIP;
+            }
+        return MATO_OK;
+    };
+    const mato_status status = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(x);
+    if (status == MATO_OK) *ms_per_update = (double)ms / iters;
     return status;
 }

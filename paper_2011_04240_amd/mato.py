@@ -113,6 +113,7 @@ SIGNATURES = {
     "mato_get_state": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
     "mato_stream_copy": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
+    "mato_stream_update": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
     "mato_stream_create": (_i32, [_pvp]),
     "mato_stream_destroy": (_i32, [_vp]),
 }
@@ -433,6 +434,12 @@ def mato_solve_destroy(solve):
 def mato_stream_copy(nbytes, grid=1024, iters=10, stream=None):
     ms = _f64()
     _check(lib().mato_stream_copy(nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def mato_stream_update(nbytes, grid=1024, iters=10, stream=None):
+    ms = _f64()
+    _check(lib().mato_stream_update(nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
     return ms.value
 
 

@@ -236,6 +236,11 @@ def test_stream_copy_probe():
     with pytest.raises(mato.MatoError) as e:
         mato.mato_stream_copy(15, 256, 1)
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
+    ms = mato.mato_stream_update(1 << 24, 256, 3)
+    assert ms > 0
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_stream_update(1 << 24, 0, 1)
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
 
 
 def test_batches_on_library_streams():
