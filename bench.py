@@ -106,12 +106,14 @@ def traffic_from_counters():
         return None
 
 
-def cpu_baseline(n, T, seconds):
-    """The FP64 oracle on one problem of the same workload, BLAS limited to one thread."""
+def _oracle_iterations(job):
+    """The FP64 oracle iterating one random-box problem (seed `seed`) for about `seconds`,
+    BLAS limited to one thread.  Returns (iterations, seconds).  Runs in a pool worker."""
+    n, T, seconds, seed = job
     from threadpoolctl import threadpool_limits
     from oracle import am
     from paper_2011_04240_amd import scenarios as sc
-    s, g = sc.random_box(n, seed=0)
+    s, g = sc.random_box(n, seed=seed)
     with threadpool_limits(limits=1):
         plan = am.make_plan(n, T, 11, 10.0, 0.3, 0.6, 1.0)
         st = am.initial_state(plan, s, g)
@@ -122,10 +124,58 @@ def cpu_baseline(n, T, seconds):
             st = am.iterate(plan, st)
             iters += 1
         dt = time.perf_counter() - t0
-    upd = n * (n - 1) // 2 * T * iters / dt
-    return {"value": upd, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": "one n=%d T=%d random-box problem, %d FP64 iterations in %.1f s, BLAS 1 thread"
-                      % (n, T, iters, dt)}
+    return iters, dt
+
+
+def host_cores():
+    """Cores this process may run on, at most 16 (the host share of one GPU)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(16, c))
+
+
+def start_cpu_pool():
+    """Worker processes for the oracle baseline, started before anything touches the GPU
+    (fresh interpreters, one BLAS thread each); None if they cannot be started."""
+    import multiprocessing
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    try:
+        for k in saved:
+            os.environ[k] = "1"
+        pool = multiprocessing.get_context("spawn").Pool(host_cores())
+        pool.cores = host_cores()
+        return pool
+    except (OSError, RuntimeError, ValueError):
+        return None
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def cpu_baseline(n, T, seconds, pool=None):
+    """The FP64 oracle on the host: one problem of the workload per core (seeds 0..C-1),
+    all cores at once for 2 * seconds of CPU time in all (at least 2 s each), aggregate
+    updates/s; in this process on one core for `seconds` without a pool."""
+    npairs = n * (n - 1) // 2
+    if pool is None:
+        iters, dt = _oracle_iterations((n, T, seconds, 0))
+        return {"value": npairs * T * iters / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                "sample": "one n=%d T=%d random-box problem, %d FP64 iterations in %.1f s, BLAS 1 thread"
+                          % (n, T, iters, dt)}
+    cores = pool.cores
+    per = max(2.0, 2.0 * seconds / cores)
+    res = pool.map(_oracle_iterations, [(n, T, per, q) for q in range(cores)], chunksize=1)
+    rates = [npairs * T * it / dt for it, dt in res]
+    return {"value": float(sum(rates)), "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "per_core": float(np.mean(rates)),
+            "sample": "%d processes at once, each one n=%d T=%d random-box problem (seeds 0..%d) iterated in FP64 "
+                      "for %.1f s (%d-%d iterations each), BLAS 1 thread per process"
+                      % (cores, n, T, cores - 1, per, min(r[0] for r in res), max(r[0] for r in res))}
 
 
 RHO_SCHEDULE = ([2.0 ** j for j in range(10)], [30 * j for j in range(10)])
@@ -384,8 +434,8 @@ def copy_calibration(mib):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the problems are independent and this build "
-              "has no multi-GPU path (see the sharding design); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the problems are independent and the library "
+              "has no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -401,6 +451,16 @@ def main():
         print(json.dumps({"metric": "served p50/p99 solve latency", "unit": "ms", "sweep": sweep,
                           "data": "synthetic", "n_gpus": 1}))
         return
+    pool = None if args.no_cpu_baseline else start_cpu_pool()     # before the GPU is initialised
+    try:
+        run_main(args, pool)
+    finally:
+        if pool is not None:
+            pool.terminate()
+            pool.join()
+
+
+def run_main(args, pool):
     import torch
     from paper_2011_04240_amd import mato
     from paper_2011_04240_amd import scenarios as sc
@@ -484,7 +544,7 @@ def main():
     if not args.no_mixed:
         out["solve_times"] = solve_times()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, T, args.cpu_seconds, pool)
     print(json.dumps(out))
 
 
