@@ -58,6 +58,7 @@ typedef int32_t mato_status;
                                         n(n-1)/2 pairs in LDS                                  */
 #define MATO_MAX_STAGES 16           /* largest number of stages of a rho schedule             */
 #define MATO_MAX_OBSTACLES 1024      /* largest number of static obstacles per problem         */
+#define MATO_HISTORY_CAP 4096        /* per-problem residual history entries kept on the device */
 
 /* Trajectory basis of eq. (param): Bernstein polynomials of degree n_coef-1 over
  * [0, t_final] seconds, sampled at T uniformly spaced instants including both ends. */
@@ -201,7 +202,9 @@ mato_status mato_batch_coeffs(mato_batch batch, int32_t q, double* c);
 
 /* Per-iteration history of problem q: max and RMS of ||f_c||_2 over pairs and
  * instants (metres) and the smoothness cost sum ||p-ddot||^2 of eq. (cost_proposed).
- * Writes min(cap, iterations) entries; any output pointer may be NULL. */
+ * Writes min(cap, iterations, MATO_HISTORY_CAP) entries; any output pointer may be
+ * NULL.  The device keeps the first MATO_HISTORY_CAP - 1 iterations, and its last
+ * entry follows the latest iteration once more have been taken. */
 mato_status mato_batch_residuals(mato_batch batch, int32_t q, double* r_max, double* r_rms,
                                  double* cost, int32_t cap, int32_t* n_written);
 
@@ -333,7 +336,10 @@ mato_status mato_server_run_trace(mato_server s, int32_t count, const double* ar
                                   double* wall_s);
 
 /* ------------------------------------------------------ single problem ---
- * Convenience wrappers: a solve is a batch of one (same handle type). */
+ * Convenience wrappers: a solve is a batch of one (same handle type).
+ * mato_solve_run creates the solve and runs it as mato_batch_run; if the run itself
+ * fails (NONFINITE, HIP) *out still holds the solve, for inspection, and the caller
+ * destroys it; if creation fails *out is NULL. */
 typedef struct mato_batch_s* mato_solve;
 mato_status mato_solve_run(mato_plan plan, const double* starts, const double* goals,
                            int32_t iters, double tol, int32_t check_every, mato_solve* out);

@@ -5,6 +5,8 @@
 
 namespace mato {
 
+static_assert(kHistCap == MATO_HISTORY_CAP, "device history capacity differs from the header's");
+
 template <typename S>
 using BatchImpl = Engine<S>;
 

@@ -591,10 +591,12 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         const double s2 = glob((const double*)Dp->misc)[0];
         const int itn = ctrl[0];
         const double rmax = sqrt(mx);
-        if (itn < Dp->hist_cap) {
-            hist[(size_t)itn * 3 + 0] = rmax;
-            hist[(size_t)itn * 3 + 1] = sqrt(s1 / ((double)Dp->np * (double)T));
-            hist[(size_t)itn * 3 + 2] = s2;
+        {
+            // the first hist_cap - 1 iterations, then the last entry follows the latest one
+            const size_t h = (size_t)min(itn, Dp->hist_cap - 1) * 3;
+            hist[h + 0] = rmax;
+            hist[h + 1] = sqrt(s1 / ((double)Dp->np * (double)T));
+            hist[h + 2] = s2;
         }
         ctrl[0] = itn + 1;
         if (!isfinite(s1) || !isfinite(s2)) {

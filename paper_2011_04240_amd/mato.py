@@ -27,6 +27,7 @@ MATO_WARN_NOT_CONVERGED = 1
 MATO_MAX_AGENTS = 160
 MATO_MAX_STAGES = 16
 MATO_MAX_OBSTACLES = 1024
+MATO_HISTORY_CAP = 4096
 
 MATO_FP64, MATO_FP32, MATO_BF16_REFINED = 0, 1, 2
 PRECISIONS = {"fp64": MATO_FP64, "fp32": MATO_FP32, "bf16": MATO_BF16_REFINED}

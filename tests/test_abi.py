@@ -34,6 +34,14 @@ def test_binding_covers_the_header():
     assert set(mato.SIGNATURES) == _declared()
 
 
+def test_binding_constants_match_the_header():
+    txt = open(os.path.join(ROOT, "include", "mato.h")).read()
+    defines = dict(re.findall(r"#define\s+(MATO_[A-Z0-9_]+)\s+(-?\d+)\b", txt))
+    assert len(defines) >= 12
+    for name, value in defines.items():
+        assert getattr(mato, name) == int(value), name
+
+
 def test_version_string():
     assert "gfx950" in mato.mato_version()
 

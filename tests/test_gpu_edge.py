@@ -266,3 +266,32 @@ def test_batches_on_library_streams():
     b2.close()
     s1.close()
     s2.close()
+
+
+def test_history_keeps_latest_beyond_capacity():
+    """Past MATO_HISTORY_CAP iterations the history keeps its first entries and its last
+    entry follows the latest iteration: equal to the first entry of a fresh problem
+    resumed from the state one iteration earlier and stepped once."""
+    say("history beyond capacity")
+    cap = mato.MATO_HISTORY_CAP
+    s, g = sc.swap_circle(4, seed=5)
+    p = mato.Plan(4, 20, 11, 5.0, 0.4, 0.8, 1.0, "fp32")
+    b = mato.Batch([p], [s], [g])
+    b.step(cap - 1)
+    head = [np.copy(x) for x in b.residuals(0)]
+    assert len(head[0]) == cap - 1
+    b.step(4)                            # iterations cap .. cap + 3 overwrite the last entry
+    b.debug(True)
+    b.step(1)                            # iteration cap + 4 leaves proj for the resume
+    st = b.get_state(0, proj=True)
+    b.step(1)                            # iteration cap + 5: the latest
+    r = b.residuals(0)
+    assert b.status(0)[0] == cap + 5 and len(r[0]) == cap
+    for x, y in zip(r, head):
+        np.testing.assert_array_equal(x[:cap - 1], y)
+    fresh = mato.Batch([p], [s], [g])
+    fresh.set_state(0, st["c"], st["lam"], st["proj"])
+    fresh.step(1)
+    one = fresh.residuals(0)
+    for x, y in zip(r, one):
+        assert x[cap - 1] == y[-1]
