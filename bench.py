@@ -71,6 +71,9 @@ def parse():
                     help="replay the server's iterations from HIP graphs (recaptured when the resident set changes)")
     ap.add_argument("--serve-fixed-rho", action="store_true",
                     help="serve with one rho instead of the increasing schedule")
+    ap.add_argument("--config-solves", action="store_true",
+                    help="only time whole fixed-iteration solves of single problems of the four single-problem "
+                         "configurations, on the GPU and by the oracle on the host")
     return ap.parse_args()
 
 
@@ -327,6 +330,82 @@ def solve_times(ns=(8, 16, 32), seeds=4):
     return out
 
 
+# single-problem configurations: label, n, T, t_final, a, b, iterations, precision, scenario
+CONFIG_SOLVES = [
+    ("swap circle n=4 T=50 FP64, 200 iterations", 4, 50, 5.0, 0.4, 0.8, 200, "fp64", "circle"),
+    ("swap sphere n=16 T=100 FP32, 300 iterations", 16, 100, 10.0, 0.3, 0.6, 300, "fp32", "sphere"),
+    ("random box n=64 T=100 FP32, 300 iterations", 64, 100, 10.0, 0.3, 0.6, 300, "fp32", "box"),
+    ("random box n=64 T=100 BF16 split + FP64 correction, 300 iterations", 64, 100, 10.0, 0.3, 0.6, 300, "bf16",
+     "box"),
+]
+
+
+def _config_scenario(kind, n, seed):
+    from paper_2011_04240_amd import scenarios as sc
+    if kind == "circle":
+        return sc.swap_circle(n, seed=seed)
+    if kind == "sphere":
+        return sc.swap_sphere(n, seed=seed)
+    return sc.random_box(n, seed=seed)
+
+
+def _oracle_config_solve(job):
+    """Plan and whole fixed-iteration solves of one configuration by the FP64 oracle, one
+    BLAS thread (pool worker): plan seconds and the median of `runs` solves after `warm`."""
+    n, T, tf, a, b, iters, kind, warm, runs = job
+    from threadpoolctl import threadpool_limits
+    from oracle import am
+    s, g = _config_scenario(kind, n, 0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        plan = am.make_plan(n, T, 11, tf, a, b, 1.0)
+        plan_s = time.perf_counter() - t0
+        times = []
+        for k in range(warm + runs):
+            t0 = time.perf_counter()
+            am.solve(plan, s, g, iters)
+            if k >= warm:
+                times.append(time.perf_counter() - t0)
+    return plan_s, float(np.median(times))
+
+
+def config_solves(pool):
+    """Whole fixed-iteration solves of single problems of the specified configurations, on
+    the GPU (batch of one: creation, initialisation, iterations, coefficients back; plan
+    built beforehand and timed apart; one warm-up, median of 5) and by the FP64 oracle on
+    the host (one BLAS thread per process, the configurations in parallel)."""
+    from paper_2011_04240_amd import mato
+    jobs = [(n, T, tf, a, b, it, kind, 1 if n >= 64 else 3, 3 if n >= 64 else 5)
+            for _, n, T, tf, a, b, it, _, kind in CONFIG_SOLVES]
+    cpu = pool.map_async(_oracle_config_solve, jobs, chunksize=1) if pool is not None else None
+    out = []
+    for label, n, T, tf, a, b, iters, prec, kind in CONFIG_SOLVES:
+        s, g = _config_scenario(kind, n, 0)
+        t0 = time.perf_counter()
+        plan = mato.Plan(n, T, 11, tf, a, b, 1.0, prec)
+        plan_s = time.perf_counter() - t0
+        times = []
+        for k in range(6):
+            t0 = time.perf_counter()
+            bt = mato.Batch([plan], [s], [g])
+            bt.run(iters, 0.0, iters)
+            bt.coeffs(0)
+            times.append(time.perf_counter() - t0)
+            bt.close()
+        plan.close()
+        gpu_s = float(np.median(times[1:]))
+        upd = n * (n - 1) // 2 * T * iters
+        out.append({"config": label, "gpu_plan_s": plan_s, "gpu_solve_s": gpu_s, "gpu_updates_per_s": upd / gpu_s})
+        print(f"{label}: GPU {gpu_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    if cpu is not None:
+        for row, job, (plan_s, sec) in zip(out, jobs, cpu.get()):
+            n, T, iters = job[0], job[1], job[5]
+            row.update({"oracle_plan_s": plan_s, "oracle_solve_s": sec,
+                        "oracle_updates_per_s": n * (n - 1) // 2 * T * iters / sec,
+                        "oracle_s_per_iteration": sec / iters, "speedup": sec / row["gpu_solve_s"]})
+    return out
+
+
 def obstacle_scaling(n=16, counts=(0, 8, 16, 32, 64, 128), batch=256, iters=30):
     """Iteration time against the number of static obstacles (16 agents, T = 100): one
     problem alone and `batch` problems per launch; structured solve, FP32, graphs."""
@@ -453,6 +532,13 @@ def main():
         return
     pool = None if args.no_cpu_baseline else start_cpu_pool()     # before the GPU is initialised
     try:
+        if args.config_solves:
+            import torch
+            torch.cuda.set_device(0)
+            print(json.dumps({"metric": "whole solve seconds of single problems", "data": "synthetic", "n_gpus": 1,
+                              "oracle_cores": pool.cores if pool is not None else 0,
+                              "configs": config_solves(pool)}))
+            return
         run_main(args, pool)
     finally:
         if pool is not None:
