@@ -95,6 +95,18 @@ struct Engine {
         int iters_host = 0;                  // iterations enqueued since attach
         std::vector<double> starts, goals;   // [n][3]
         std::vector<double> obstacles;       // [n_obs][5]: x, y, z, l_xy, l_z
+        // host sources of this slot's uploads: they stay valid until the slot is attached
+        // again, so the copies need no wait
+        int ctrl_init[kCtrl] = {0};
+        struct StageSrc {
+            ProblemDesc<S> desc;
+            double* kinv = nullptr;
+        };
+        StageSrc stage_src[kMaxStages];      // per stage: written once per attach (never moves)
+        std::vector<double> hq;
+        std::vector<float> hf;
+        std::vector<S> ho;
+        std::vector<WorkItem> hinit;
     };
 
     int precision = MATO_FP32;
@@ -123,6 +135,7 @@ struct Engine {
 
     std::vector<GemmGroup> hgroups;
     std::vector<GemmTile> htiles;
+    std::vector<GemmCol> hcolq, hcolr;
     GemmGroup* dgroups = nullptr;
     GemmTile* dtiles = nullptr;
     GemmCol* dcolsq = nullptr;
@@ -223,6 +236,15 @@ struct Engine {
         Prob P;
         describe(P, plan);
         return P.bytes;
+    }
+
+    // Size of a slot's own device block for `bytes` of problem state: the next power of two
+    // (at least 64 KB), so that blocks freed by finished problems fit most later ones and
+    // admissions rarely allocate.
+    static size_t block_class(size_t bytes) {
+        size_t c = (size_t)1 << 16;
+        while (c < bytes) c <<= 1;
+        return c;
     }
 
     // Control words, descriptors and per-slot pointer tables for `cap` slots.
@@ -335,6 +357,8 @@ struct Engine {
 
     // Work list, product groups and tiles of the active slots.
     mato_status rebuild_lists() {
+        // the buffers below may be reallocated: nothing queued may still read them
+        MATO_HIP(hipStreamSynchronize(stream));
         hitems.clear();
         size_t maxlds = 0;
         has_obs = false;
@@ -344,7 +368,8 @@ struct Engine {
         lds = maxlds;
         MATO_TRY(ensure_device(&ditems, &ditems_cap, hitems.size()));
         if (!hitems.empty())
-            MATO_HIP(hipMemcpy(ditems, hitems.data(), sizeof(WorkItem) * hitems.size(), hipMemcpyHostToDevice));
+            MATO_HIP(hipMemcpyAsync(ditems, hitems.data(), sizeof(WorkItem) * hitems.size(), hipMemcpyHostToDevice,
+                                    stream));
         if (lds > 0 && set_pairwise_lds_limit<S>(lds) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot raise the LDS limit of the pairwise kernel to %zu bytes", lds);
@@ -357,7 +382,10 @@ struct Engine {
             if (!members.count(probs[q].plan)) order.push_back(probs[q].plan);
             members[probs[q].plan].push_back(q);
         }
-        std::vector<GemmCol> colq, colr;
+        std::vector<GemmCol>& colq = hcolq;
+        std::vector<GemmCol>& colr = hcolr;
+        colq.clear();
+        colr.clear();
         hgroups.clear();
         htiles.clear();
         for (size_t g = 0; g < order.size(); ++g) {
@@ -395,12 +423,14 @@ struct Engine {
         MATO_TRY(ensure_device(&dcolsq, &cap_colsq, colq.size()));
         MATO_TRY(ensure_device(&dcolsr, &cap_colsr, colr.size()));
         if (!hgroups.empty()) {
-            MATO_HIP(hipMemcpy(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size(), hipMemcpyHostToDevice));
-            MATO_HIP(hipMemcpy(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size(), hipMemcpyHostToDevice));
-            MATO_HIP(hipMemcpy(dcolsq, colq.data(), sizeof(GemmCol) * colq.size(), hipMemcpyHostToDevice));
-            MATO_HIP(hipMemcpy(dcolsr, colr.data(), sizeof(GemmCol) * colr.size(), hipMemcpyHostToDevice));
+            MATO_HIP(hipMemcpyAsync(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size(), hipMemcpyHostToDevice,
+                                    stream));
+            MATO_HIP(hipMemcpyAsync(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size(), hipMemcpyHostToDevice,
+                                    stream));
+            MATO_HIP(hipMemcpyAsync(dcolsq, colq.data(), sizeof(GemmCol) * colq.size(), hipMemcpyHostToDevice, stream));
+            MATO_HIP(hipMemcpyAsync(dcolsr, colr.data(), sizeof(GemmCol) * colr.size(), hipMemcpyHostToDevice, stream));
         }
-        MATO_TRY(upload_desc());          // slab counts may have changed
+        MATO_TRY(upload_desc());          // slab counts may have changed; waits for the copies above
         drop_graphs();
         lists_dirty = false;
         return MATO_OK;
@@ -423,14 +453,15 @@ struct Engine {
                 if (P.own) dfree(P.base);
                 P.base = nullptr;
                 P.own = false;
-                if (hipMalloc(&P.base, P.bytes) != hipSuccess) {
+                const size_t cap = block_class(P.bytes);
+                if (hipMalloc(&P.base, cap) != hipSuccess) {
                     (void)hipGetLastError();
                     P.base = nullptr;
-                    set_error("device allocation of %zu bytes failed", P.bytes);
+                    set_error("device allocation of %zu bytes failed", cap);
                     return MATO_ERR_OUT_OF_MEMORY;
                 }
                 P.own = true;
-                P.block = P.bytes;
+                P.block = cap;
             }
             MATO_HIP(hipMemsetAsync(P.base, 0, P.bytes, stream));
         }
@@ -462,7 +493,6 @@ struct Engine {
         hkinv[q] = plan->dKinv;
         MATO_HIP(hipMemcpyAsync(dk0c + q, &hk0c[q], sizeof(double*), hipMemcpyHostToDevice, stream));
         MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipStreamSynchronize(stream));
         lists_dirty = true;
         return MATO_OK;
     }
@@ -472,9 +502,8 @@ struct Engine {
         Prob& P = probs[q];
         if (!P.active) return MATO_OK;
         P.active = false;
-        int z[kCtrl] = {0};
-        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, z, sizeof(z), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipStreamSynchronize(stream));
+        static const int zero[kCtrl] = {0};
+        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, zero, sizeof(zero), hipMemcpyHostToDevice, stream));
         lists_dirty = true;
         return MATO_OK;
     }
@@ -493,8 +522,9 @@ struct Engine {
     // Boundary rows of q: [start, 0, 0, goal, 0, 0] per agent and axis, FP64 and FP32;
     // and the obstacle table.
     mato_status upload_beq(int q) {
-        const Prob& P = probs[q];
-        std::vector<S> ho((size_t)kObs * P.n_obs, S(0));      // kept until the synchronisation below
+        Prob& P = probs[q];
+        std::vector<S>& ho = P.ho;
+        ho.assign((size_t)kObs * P.n_obs, S(0));
         if (P.n_obs > 0) {
             for (int o = 0; o < P.n_obs; ++o) {
                 const double* ob = &P.obstacles[(size_t)5 * o];
@@ -504,24 +534,25 @@ struct Engine {
             }
             MATO_HIP(hipMemcpyAsync(P.base + P.o_obs, ho.data(), sizeof(S) * ho.size(), hipMemcpyHostToDevice, stream));
         }
-        std::vector<double> hq((size_t)3 * P.ldq, 0.0);
+        std::vector<double>& hq = P.hq;
+        hq.assign((size_t)3 * P.ldq, 0.0);
         for (int a = 0; a < 3; ++a)
             for (int i = 0; i < P.n; ++i) {
                 double* b = &hq[(size_t)a * P.ldq + (size_t)P.n * P.nv + (size_t)i * kNb];
                 b[0] = P.starts[(size_t)i * 3 + a];
                 b[3] = P.goals[(size_t)i * 3 + a];
             }
-        std::vector<float> hf(hq.begin(), hq.end());
+        P.hf.assign(hq.begin(), hq.end());
         MATO_HIP(hipMemcpyAsync(P.base + P.o_q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipMemcpyAsync(P.base + P.o_qf, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipStreamSynchronize(stream));
+        MATO_HIP(hipMemcpyAsync(P.base + P.o_qf, P.hf.data(), sizeof(float) * P.hf.size(), hipMemcpyHostToDevice, stream));
         return MATO_OK;
     }
 
     mato_status reset_ctrl(int q) {
-        int w[kCtrl] = {0};
+        int* w = probs[q].ctrl_init;
+        for (int k = 0; k < kCtrl; ++k) w[k] = 0;
         w[3] = 1;
-        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, w, sizeof(w), hipMemcpyHostToDevice, stream));
+        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, w, sizeof(int) * kCtrl, hipMemcpyHostToDevice, stream));
         return MATO_OK;
     }
 
@@ -547,12 +578,16 @@ struct Engine {
         if (lists_dirty) MATO_TRY(rebuild_lists());
         MATO_TRY(reset_ctrl(q));
         MATO_TRY(upload_beq(q));
-        std::vector<WorkItem> items;
+        std::vector<WorkItem>& items = probs[q].hinit;
+        items.clear();
         size_t l = 0;
         slot_items(q, items, &l, 0);
-        MATO_TRY(ensure_device(&dscratch, &dscratch_cap, items.size()));
+        if (dscratch_cap < items.size()) {
+            // the list of an earlier slot's initialisation may still be in use: let it finish first
+            MATO_HIP(hipStreamSynchronize(stream));
+            MATO_TRY(ensure_device(&dscratch, &dscratch_cap, std::max<size_t>(items.size(), (size_t)probs[q].T)));
+        }
         MATO_HIP(hipMemcpyAsync(dscratch, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipStreamSynchronize(stream));
         const int nv = probs[q].nv == 11 ? 11 : 0;
         const ProblemDesc<S>* d = ddesc + q;
         MATO_HIP(launch_init<S>(d, dk0c + q, 1, stream));
@@ -667,24 +702,35 @@ struct Engine {
             if (P.iters_host != P.stage_start[P.stage + 1]) continue;
             P.stage += 1;
             P.plan = P.stages[P.stage];
-            hkinv[q] = P.plan->dKinv;
-            MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
             moved.push_back(q);
         }
         if (moved.empty()) return MATO_OK;
-        MATO_HIP(hipStreamSynchronize(stream));
         if (solve == MATO_SOLVE_STRUCTURED) {
-            // only the moved slots' descriptors change (rho, the per-agent inverses): the
-            // work lists and any captured graphs stay valid
+            // only the moved slots' descriptors change (rho, the per-agent inverses): the work
+            // lists and any captured graphs stay valid, and the uploads are stream-ordered after
+            // the iterations already queued, from host sources that are not reused before the
+            // slot is attached again
             for (int q : moved) {
+                Prob& P = probs[q];
                 fill_desc(q);
-                MATO_HIP(hipMemcpyAsync(ddesc + q, &hdesc[q], sizeof(ProblemDesc<S>), hipMemcpyHostToDevice, stream));
+                auto& src = P.stage_src[P.stage];
+                src.desc = hdesc[q];
+                src.kinv = P.plan->dKinv;
+                hkinv[q] = P.plan->dKinv;
+                MATO_HIP(hipMemcpyAsync(dkinv + q, &src.kinv, sizeof(double*), hipMemcpyHostToDevice, stream));
+                MATO_HIP(hipMemcpyAsync(ddesc + q, &src.desc, sizeof(ProblemDesc<S>), hipMemcpyHostToDevice, stream));
             }
-            MATO_HIP(hipStreamSynchronize(stream));
         } else {
+            MATO_HIP(hipStreamSynchronize(stream));
+            for (int q : moved) {
+                hkinv[q] = probs[q].plan->dKinv;
+                MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
+            }
             MATO_TRY(rebuild_lists());        // the product groups follow the plans
         }
-        for (int q : moved) MATO_HIP(launch_ceq<S>(ddesc + q, dkinv + q, 1, stream));
+        // c_eq of the moved slots in one launch over every slot (for the others it is
+        // recomputed from the same plan and boundary data, so it does not change)
+        MATO_HIP(launch_ceq<S>(ddesc, dkinv, count(), stream));
         return MATO_OK;
     }
 

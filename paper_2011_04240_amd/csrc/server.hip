@@ -221,15 +221,17 @@ struct ServerOps {
             const mato_plan plan = sp[0];
             const size_t need = Engine<S>::slot_bytes(plan);
             int q = -1;
-            for (int k = 0; k < e->count() && q < 0; ++k)      // a free slot whose block fits
-                if (s->slot_req[k] < 0 && !e->probs[k].active && e->probs[k].own && e->probs[k].block >= need) q = k;
+            for (int k = 0; k < e->count(); ++k)                // the free slot with the smallest block that fits
+                if (s->slot_req[k] < 0 && !e->probs[k].active && e->probs[k].own && e->probs[k].block >= need &&
+                    (q < 0 || e->probs[k].block < e->probs[q].block))
+                    q = k;
             for (int k = 0; k < e->count() && q < 0; ++k)      // any free slot
                 if (s->slot_req[k] < 0 && !e->probs[k].active) q = k;
             if (q < 0) break;
             const bool reuse = e->probs[q].own && e->probs[q].block >= need;
             if (!reuse) {
                 e->release_block(q);
-                if (!make_room(s, need, sp, q)) {
+                if (!make_room(s, Engine<S>::block_class(need), sp, q)) {
                     if (e->active_count() == 0) {
                         reject(s, MATO_ERR_OUT_OF_MEMORY,
                                "the device-memory budget cannot hold this request's plans and state together");
