@@ -95,18 +95,6 @@ struct Engine {
         int iters_host = 0;                  // iterations enqueued since attach
         std::vector<double> starts, goals;   // [n][3]
         std::vector<double> obstacles;       // [n_obs][5]: x, y, z, l_xy, l_z
-        // host sources of this slot's uploads: they stay valid until the slot is attached
-        // again, so the copies need no wait
-        int ctrl_init[kCtrl] = {0};
-        struct StageSrc {
-            ProblemDesc<S> desc;
-            double* kinv = nullptr;
-        };
-        StageSrc stage_src[kMaxStages];      // per stage: written once per attach (never moves)
-        std::vector<double> hq;
-        std::vector<float> hf;
-        std::vector<S> ho;
-        std::vector<WorkItem> hinit;
     };
 
     int precision = MATO_FP32;
@@ -123,7 +111,7 @@ struct Engine {
     ProblemDesc<S>* ddesc = nullptr;
     double** dk0c = nullptr;
     double** dkinv = nullptr;
-    std::vector<double*> hk0c, hkinv;        // host copies: the source of every upload of a slot's pointers
+    std::vector<double*> hk0c, hkinv;        // host copies of the per-slot pointer tables
 
     std::vector<WorkItem> hitems;
     WorkItem* ditems = nullptr;
@@ -135,7 +123,6 @@ struct Engine {
 
     std::vector<GemmGroup> hgroups;
     std::vector<GemmTile> htiles;
-    std::vector<GemmCol> hcolq, hcolr;
     GemmGroup* dgroups = nullptr;
     GemmTile* dtiles = nullptr;
     GemmCol* dcolsq = nullptr;
@@ -152,6 +139,12 @@ struct Engine {
     hipGraphExec_t g1 = nullptr, gC = nullptr;
     static constexpr int kChunk = 16;
 
+    // pinned staging ring of the host-to-device uploads: a region is reused only after the
+    // stream has been waited on, so the copies need neither a wait nor a live host source
+    static constexpr size_t kRingBytes = (size_t)1 << 20;
+    char* ring = nullptr;
+    size_t ring_off = 0;
+
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> pw_events;       // pairs around pairwise launches
@@ -159,6 +152,7 @@ struct Engine {
     bool last_timed = false;
 
     ~Engine() {
+        if (ring) (void)hipHostFree(ring);
         if (g1) (void)hipGraphExecDestroy(g1);
         if (gC) (void)hipGraphExecDestroy(gC);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -182,6 +176,28 @@ struct Engine {
     }
 
     int count() const { return (int)probs.size(); }
+
+    // Stream-ordered copy of `bytes` host bytes to `dst`; `src` may be reused on return.
+    mato_status upload(void* dst, const void* src, size_t bytes) {
+        if (bytes == 0) return MATO_OK;
+        if (!ring && hipHostMalloc((void**)&ring, kRingBytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ring = nullptr;
+        }
+        if (!ring || bytes > kRingBytes / 2) {           // no ring, or too large for it: copy and wait
+            MATO_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+            MATO_HIP(hipStreamSynchronize(stream));
+            return MATO_OK;
+        }
+        if (ring_off + bytes > kRingBytes) {             // wrap: every earlier copy from the ring is done
+            MATO_HIP(hipStreamSynchronize(stream));
+            ring_off = 0;
+        }
+        memcpy(ring + ring_off, src, bytes);
+        MATO_HIP(hipMemcpyAsync(dst, ring + ring_off, bytes, hipMemcpyHostToDevice, stream));
+        ring_off = (ring_off + bytes + 255) & ~(size_t)255;
+        return MATO_OK;
+    }
 
     int active_count() const {
         int k = 0;
@@ -319,8 +335,7 @@ struct Engine {
 
     mato_status upload_desc() {
         for (int q = 0; q < count(); ++q) fill_desc(q);
-        MATO_HIP(hipMemcpyAsync(ddesc, hdesc.data(), sizeof(ProblemDesc<S>) * count(), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipStreamSynchronize(stream));
+        MATO_TRY(upload(ddesc, hdesc.data(), sizeof(ProblemDesc<S>) * count()));
         return MATO_OK;
     }
 
@@ -368,8 +383,7 @@ struct Engine {
         lds = maxlds;
         MATO_TRY(ensure_device(&ditems, &ditems_cap, hitems.size()));
         if (!hitems.empty())
-            MATO_HIP(hipMemcpyAsync(ditems, hitems.data(), sizeof(WorkItem) * hitems.size(), hipMemcpyHostToDevice,
-                                    stream));
+            MATO_TRY(upload(ditems, hitems.data(), sizeof(WorkItem) * hitems.size()));
         if (lds > 0 && set_pairwise_lds_limit<S>(lds) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot raise the LDS limit of the pairwise kernel to %zu bytes", lds);
@@ -382,10 +396,7 @@ struct Engine {
             if (!members.count(probs[q].plan)) order.push_back(probs[q].plan);
             members[probs[q].plan].push_back(q);
         }
-        std::vector<GemmCol>& colq = hcolq;
-        std::vector<GemmCol>& colr = hcolr;
-        colq.clear();
-        colr.clear();
+        std::vector<GemmCol> colq, colr;
         hgroups.clear();
         htiles.clear();
         for (size_t g = 0; g < order.size(); ++g) {
@@ -423,14 +434,12 @@ struct Engine {
         MATO_TRY(ensure_device(&dcolsq, &cap_colsq, colq.size()));
         MATO_TRY(ensure_device(&dcolsr, &cap_colsr, colr.size()));
         if (!hgroups.empty()) {
-            MATO_HIP(hipMemcpyAsync(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size(), hipMemcpyHostToDevice,
-                                    stream));
-            MATO_HIP(hipMemcpyAsync(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size(), hipMemcpyHostToDevice,
-                                    stream));
-            MATO_HIP(hipMemcpyAsync(dcolsq, colq.data(), sizeof(GemmCol) * colq.size(), hipMemcpyHostToDevice, stream));
-            MATO_HIP(hipMemcpyAsync(dcolsr, colr.data(), sizeof(GemmCol) * colr.size(), hipMemcpyHostToDevice, stream));
+            MATO_TRY(upload(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size()));
+            MATO_TRY(upload(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size()));
+            MATO_TRY(upload(dcolsq, colq.data(), sizeof(GemmCol) * colq.size()));
+            MATO_TRY(upload(dcolsr, colr.data(), sizeof(GemmCol) * colr.size()));
         }
-        MATO_TRY(upload_desc());          // slab counts may have changed; waits for the copies above
+        MATO_TRY(upload_desc());          // slab counts may have changed
         drop_graphs();
         lists_dirty = false;
         return MATO_OK;
@@ -491,8 +500,8 @@ struct Engine {
         P.active = true;
         hk0c[q] = plan->dK0c;
         hkinv[q] = plan->dKinv;
-        MATO_HIP(hipMemcpyAsync(dk0c + q, &hk0c[q], sizeof(double*), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
+        MATO_TRY(upload(dk0c + q, &hk0c[q], sizeof(double*)));
+        MATO_TRY(upload(dkinv + q, &hkinv[q], sizeof(double*)));
         lists_dirty = true;
         return MATO_OK;
     }
@@ -502,8 +511,8 @@ struct Engine {
         Prob& P = probs[q];
         if (!P.active) return MATO_OK;
         P.active = false;
-        static const int zero[kCtrl] = {0};
-        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, zero, sizeof(zero), hipMemcpyHostToDevice, stream));
+        const int zero[kCtrl] = {0};
+        MATO_TRY(upload(dctrl + kCtrl * q, zero, sizeof(zero)));
         lists_dirty = true;
         return MATO_OK;
     }
@@ -522,37 +531,34 @@ struct Engine {
     // Boundary rows of q: [start, 0, 0, goal, 0, 0] per agent and axis, FP64 and FP32;
     // and the obstacle table.
     mato_status upload_beq(int q) {
-        Prob& P = probs[q];
-        std::vector<S>& ho = P.ho;
-        ho.assign((size_t)kObs * P.n_obs, S(0));
+        const Prob& P = probs[q];
         if (P.n_obs > 0) {
+            std::vector<S> ho((size_t)kObs * P.n_obs, S(0));
             for (int o = 0; o < P.n_obs; ++o) {
                 const double* ob = &P.obstacles[(size_t)5 * o];
                 S* e = &ho[(size_t)kObs * o];
                 e[0] = (S)ob[0]; e[1] = (S)ob[1]; e[2] = (S)ob[2];
                 e[3] = (S)(1.0 / (ob[3] * ob[3])); e[4] = (S)(1.0 / (ob[4] * ob[4])); e[5] = (S)ob[4];
             }
-            MATO_HIP(hipMemcpyAsync(P.base + P.o_obs, ho.data(), sizeof(S) * ho.size(), hipMemcpyHostToDevice, stream));
+            MATO_TRY(upload(P.base + P.o_obs, ho.data(), sizeof(S) * ho.size()));
         }
-        std::vector<double>& hq = P.hq;
-        hq.assign((size_t)3 * P.ldq, 0.0);
+        std::vector<double> hq((size_t)3 * P.ldq, 0.0);
         for (int a = 0; a < 3; ++a)
             for (int i = 0; i < P.n; ++i) {
                 double* b = &hq[(size_t)a * P.ldq + (size_t)P.n * P.nv + (size_t)i * kNb];
                 b[0] = P.starts[(size_t)i * 3 + a];
                 b[3] = P.goals[(size_t)i * 3 + a];
             }
-        P.hf.assign(hq.begin(), hq.end());
-        MATO_HIP(hipMemcpyAsync(P.base + P.o_q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, stream));
-        MATO_HIP(hipMemcpyAsync(P.base + P.o_qf, P.hf.data(), sizeof(float) * P.hf.size(), hipMemcpyHostToDevice, stream));
+        const std::vector<float> hf(hq.begin(), hq.end());
+        MATO_TRY(upload(P.base + P.o_q, hq.data(), sizeof(double) * hq.size()));
+        MATO_TRY(upload(P.base + P.o_qf, hf.data(), sizeof(float) * hf.size()));
         return MATO_OK;
     }
 
     mato_status reset_ctrl(int q) {
-        int* w = probs[q].ctrl_init;
-        for (int k = 0; k < kCtrl; ++k) w[k] = 0;
+        int w[kCtrl] = {0};
         w[3] = 1;
-        MATO_HIP(hipMemcpyAsync(dctrl + kCtrl * q, w, sizeof(int) * kCtrl, hipMemcpyHostToDevice, stream));
+        MATO_TRY(upload(dctrl + kCtrl * q, w, sizeof(w)));
         return MATO_OK;
     }
 
@@ -578,8 +584,7 @@ struct Engine {
         if (lists_dirty) MATO_TRY(rebuild_lists());
         MATO_TRY(reset_ctrl(q));
         MATO_TRY(upload_beq(q));
-        std::vector<WorkItem>& items = probs[q].hinit;
-        items.clear();
+        std::vector<WorkItem> items;
         size_t l = 0;
         slot_items(q, items, &l, 0);
         if (dscratch_cap < items.size()) {
@@ -587,7 +592,7 @@ struct Engine {
             MATO_HIP(hipStreamSynchronize(stream));
             MATO_TRY(ensure_device(&dscratch, &dscratch_cap, std::max<size_t>(items.size(), (size_t)probs[q].T)));
         }
-        MATO_HIP(hipMemcpyAsync(dscratch, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, stream));
+        MATO_TRY(upload(dscratch, items.data(), sizeof(WorkItem) * items.size()));
         const int nv = probs[q].nv == 11 ? 11 : 0;
         const ProblemDesc<S>* d = ddesc + q;
         MATO_HIP(launch_init<S>(d, dk0c + q, 1, stream));
@@ -708,23 +713,18 @@ struct Engine {
         if (solve == MATO_SOLVE_STRUCTURED) {
             // only the moved slots' descriptors change (rho, the per-agent inverses): the work
             // lists and any captured graphs stay valid, and the uploads are stream-ordered after
-            // the iterations already queued, from host sources that are not reused before the
-            // slot is attached again
+            // the iterations already queued
             for (int q : moved) {
-                Prob& P = probs[q];
                 fill_desc(q);
-                auto& src = P.stage_src[P.stage];
-                src.desc = hdesc[q];
-                src.kinv = P.plan->dKinv;
-                hkinv[q] = P.plan->dKinv;
-                MATO_HIP(hipMemcpyAsync(dkinv + q, &src.kinv, sizeof(double*), hipMemcpyHostToDevice, stream));
-                MATO_HIP(hipMemcpyAsync(ddesc + q, &src.desc, sizeof(ProblemDesc<S>), hipMemcpyHostToDevice, stream));
+                hkinv[q] = probs[q].plan->dKinv;
+                MATO_TRY(upload(dkinv + q, &hkinv[q], sizeof(double*)));
+                MATO_TRY(upload(ddesc + q, &hdesc[q], sizeof(ProblemDesc<S>)));
             }
         } else {
             MATO_HIP(hipStreamSynchronize(stream));
             for (int q : moved) {
                 hkinv[q] = probs[q].plan->dKinv;
-                MATO_HIP(hipMemcpyAsync(dkinv + q, &hkinv[q], sizeof(double*), hipMemcpyHostToDevice, stream));
+                MATO_TRY(upload(dkinv + q, &hkinv[q], sizeof(double*)));
             }
             MATO_TRY(rebuild_lists());        // the product groups follow the plans
         }
