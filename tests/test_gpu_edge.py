@@ -95,6 +95,24 @@ def test_uneven_batch_matches_alone_bitwise():
         np.testing.assert_array_equal(alone.residuals(0)[0], mix.residuals(q)[0])
 
 
+def test_large_batch_uploads_match_alone_bitwise():
+    """A batch whose creation uploads several MB of boundary data (the engine's pinned staging
+    ring wraps many times, and its work list and descriptors take the large-copy path) gives every
+    problem exactly the iterates it has alone."""
+    say("large batch uploads vs alone")
+    n, count = 48, 384      # 30 KB of boundary data per problem; 38 400 work items (614 KB)
+    plan = mato.Plan(n, 100, 11, 10.0, 0.3, 0.6, 1.0, "fp32", solve="structured")
+    scen = [sc.random_density_box(n, seed=700 + q) for q in range(count)]
+    mix = mato.Batch([plan] * count, [x[0] for x in scen], [x[1] for x in scen])
+    mix.step(12, use_graph=False)
+    mix.sync()
+    for q in (0, 17, 200, count - 1):
+        alone = mato.Batch([plan], [scen[q][0]], [scen[q][1]])
+        alone.step(12, use_graph=False)
+        np.testing.assert_array_equal(alone.coeffs(0), mix.coeffs(q))
+        np.testing.assert_array_equal(alone.residuals(0)[0], mix.residuals(q)[0])
+
+
 def test_batch_matches_oracle_per_problem():
     say("uneven batch vs oracle")
     ns = [6, 11, 17]
