@@ -50,7 +50,7 @@ typedef int32_t mato_status;
 #define MATO_ERR_SINGULAR        -3  /* zero pivot or condition estimate above 1e14           */
 #define MATO_ERR_NONFINITE       -4  /* NaN or Inf in inputs or state                        */
 #define MATO_ERR_HIP             -5  /* a HIP runtime call failed                            */
-#define MATO_ERR_UNSUPPORTED     -6  /* valid request this build does not handle (e.g. n > MATO_MAX_AGENTS) */
+#define MATO_ERR_UNSUPPORTED     -6  /* valid request the library does not handle (e.g. n > MATO_MAX_AGENTS) */
 #define MATO_ERR_NOT_FOUND       -7  /* unknown request or slot id                            */
 #define MATO_WARN_NOT_CONVERGED   1  /* iteration cap reached before the residual tolerance  */
 
@@ -270,7 +270,8 @@ typedef struct {
     double     a, b, rho;          /* spheroid dimensions l_xy, l_z and the penalty rho    */
     int32_t    precision;          /* mato_precision                                       */
     int32_t    max_slots;          /* problems resident at once, >= 1                      */
-    double     hbm_budget_bytes;   /* device bytes for plans and resident problems; <= 0: no limit */
+    double     hbm_budget_bytes;   /* device bytes for plans and resident problems (a problem's
+                                      block counts at its power-of-two size class); <= 0: no limit */
     int32_t    chunk;              /* iterations per scheduling step, >= 1                 */
     int32_t    max_iters;          /* iteration cap per problem, >= 1                      */
     double     tol;                /* convergence threshold on max ||f_c|| (metres)        */
