@@ -162,7 +162,8 @@ mato_status mato_plan_inverse(mato_plan plan, double* kinv);
 /* --------------------------------------------------------------- batches ---
  * A batch holds `count` independent problems, problem q using plans[q]; problems
  * with the same plan share one K^{-1} and are advanced together as one
- * matrix-matrix product per iteration.  All plans must have the same precision.
+ * matrix-matrix product per iteration.  All plans must have the same precision and
+ * solve kind, and must stay alive (not destroyed) while the batch exists.
  * starts/goals: 3 doubles per agent per problem, problems concatenated in order
  * ([problem][agent][x,y,z]); velocities and accelerations at both ends are zero.
  * Creation runs the initialisation of Algorithm 1: multipliers 0, coefficients
