@@ -553,6 +553,9 @@ class Server:
     def run_trace(self, arrival_s, starts_list, goals_list):
         ns = np.ascontiguousarray([np.asarray(s).shape[0] for s in starts_list], np.int32)
         arr = np.ascontiguousarray(arrival_s, np.float64)
+        if len(ns) == 0:
+            wall = mato_server_run_trace(self.handle, arr, ns, None, None, None, None, None)
+            return np.zeros(0), np.zeros(0, np.int32), np.zeros(0, np.int32), wall
         starts = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64).reshape(-1, 3) for s in starts_list]))
         goals = np.ascontiguousarray(np.concatenate([np.asarray(g, np.float64).reshape(-1, 3) for g in goals_list]))
         lat = np.zeros(len(ns))

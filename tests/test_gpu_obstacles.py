@@ -171,3 +171,23 @@ def test_server_with_obstacles_alone_vs_mix():
         c, its, convs = out[k]
         assert its == it and convs == conv
         np.testing.assert_array_equal(c, b.coeffs(0))
+
+
+def test_most_obstacles_fp64():
+    """MATO_MAX_OBSTACLES static obstacles around 3 agents (3 075 collision rows): the
+    inverse and 5 FP64 iterations against the oracle."""
+    say("maximum obstacle count")
+    n, k, T_ = 3, mato.MATO_MAX_OBSTACLES, 20
+    rng = np.random.Generator(np.random.PCG64(77))
+    s = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    g = -s
+    obs = np.concatenate([rng.uniform(-20.0, 20.0, size=(k, 3)), rng.uniform(0.5, 1.0, size=(k, 2))], axis=1)
+    plan = mato.Plan(n, T_, 11, 5.0, 0.3, 0.6, 1.0, "fp64", n_obs=k)
+    ref_plan = am.make_plan(n, T_, 11, 5.0, 0.3, 0.6, 1.0, n_obs=k)
+    assert rel(plan.inverse(), ref_plan.Kinv) < 1e-10
+    ref = am.solve(ref_plan, s, g, 5, obs=obs)
+    bt = mato.Batch([plan], [s], [g], obstacles_list=[obs])
+    bt.run(5, 0.0, 5)
+    assert rel(bt.residuals(0)[0], ref.history["r_max"]) < 1e-8
+    assert rel(bt.coeffs(0), ref.c) < 1e-9
+    assert rel(bt.get_state(0)["lam"], ref.lam) < 1e-8

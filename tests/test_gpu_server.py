@@ -160,3 +160,11 @@ def test_trace_with_a_rejected_request_ends():
     lat, its, conv, wall = srv.run_trace([0.0, 0.001, 0.002], [x[0] for x in scen], [x[1] for x in scen])
     assert its[1] == 0 and conv[1] == 0
     assert its[0] > 0 and its[2] > 0 and conv[0] == 1 and conv[2] == 1
+
+
+def test_empty_trace():
+    say("server empty trace")
+    srv = mato.Server(T=T, t_final=TF, a=A, b=B, precision="fp32", max_slots=2)
+    lat, its, conv, wall = srv.run_trace([], [], [])
+    assert len(lat) == 0 and len(its) == 0 and len(conv) == 0 and wall >= 0.0
+    assert srv.stats()[2:] == (0, 0)
