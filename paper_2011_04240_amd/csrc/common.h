@@ -130,7 +130,7 @@ struct WorkItem {               // one pairwise workgroup: instants [t0, t0 + tc
     int prob, t0, tc, slab;
 };
 
-struct GemmTile {               // one 64-row x 64-column output tile of one same-plan group
+struct GemmTile {               // one 64-row output tile (64 or 48 columns) of one same-plan group
     int group, m0, col0, pad;
 };
 

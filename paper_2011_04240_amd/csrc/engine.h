@@ -42,7 +42,20 @@ template <typename S>
 hipError_t launch_init(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
 template <typename S>
 hipError_t launch_ceq(const ProblemDesc<S>*, const double* const*, int, hipStream_t);
-hipError_t launch_gemm(int, const GemmTile*, int, const GemmGroup*, const GemmCol*, int, hipStream_t);
+hipError_t launch_gemm(int, int, const GemmTile*, int, const GemmGroup*, const GemmCol*, int, hipStream_t);
+
+inline int device_cu_count() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 256;
+    }
+    return cached;
+}
 
 inline int device_lds_limit() {
     static int cached = -1;
@@ -123,6 +136,7 @@ struct Engine {
 
     std::vector<GemmGroup> hgroups;
     std::vector<GemmTile> htiles;
+    int gemm_width = 64;                     // right-hand sides per product tile (64, or 48 in FP32)
     GemmGroup* dgroups = nullptr;
     GemmTile* dtiles = nullptr;
     GemmCol* dcolsq = nullptr;
@@ -399,6 +413,18 @@ struct Engine {
         std::vector<GemmCol> colq, colr;
         hgroups.clear();
         htiles.clear();
+        // tile width: 64 right-hand sides, or 48 in FP32 when that lowers the number of
+        // tiles the busiest compute unit works through times the tile's work
+        gemm_width = 64;
+        if (precision == MATO_FP32) {
+            auto makespan = [&](int w) {
+                long tiles = 0;
+                for (const mato_plan pl : order)
+                    tiles += (long)(round_up(pl->n * pl->nv, 64) / 64) * ((3 * (long)members[pl].size() + w - 1) / w);
+                return ((tiles + device_cu_count() - 1) / device_cu_count()) * w;
+            };
+            if (!order.empty() && makespan(48) < makespan(64)) gemm_width = 48;
+        }
         for (size_t g = 0; g < order.size(); ++g) {
             const mato_plan pl = order[g];
             const auto& mem = members[pl];
@@ -426,7 +452,7 @@ struct Engine {
                 }
             hgroups.push_back(G);
             const int Mp = round_up(G.M, 64);
-            for (int c0 = 0; c0 < G.ncols; c0 += 64)
+            for (int c0 = 0; c0 < G.ncols; c0 += gemm_width)
                 for (int m0 = 0; m0 < Mp; m0 += 64) htiles.push_back(GemmTile{(int)g, m0, c0, 0});
         }
         MATO_TRY(ensure_device(&dgroups, &cap_groups, hgroups.size()));
@@ -611,12 +637,12 @@ struct Engine {
             e = launch_solve_positions<S>(ddesc, count(), nv, st);
             if (e != hipSuccess) return e;
         } else {
-            e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsq, 0, st);
+            e = launch_gemm(precision, gemm_width, dtiles, (int)htiles.size(), dgroups, dcolsq, 0, st);
             if (e != hipSuccess) return e;
             for (int k = 0; k < refine; ++k) {
                 e = launch_residual<S>(ddesc, count(), st);
                 if (e != hipSuccess) return e;
-                e = launch_gemm(precision, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
+                e = launch_gemm(precision, gemm_width, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
                 if (e != hipSuccess) return e;
             }
             e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);

@@ -196,6 +196,112 @@ __global__ __launch_bounds__(512) void gemm_f32(const GemmTile* __restrict__ til
     finish_tile(t, G, cols, acc, smem, grp, wq, lane, accumulate);
 }
 
+// The same product over 64-row x 48-column tiles (chosen when it balances the tiles
+// over the compute units better, e.g. 704 instead of 528 tiles at n = 64 and 1024
+// problems): wave wq of a group owns rows 16 wq .. 16 wq + 15 and all 48 columns
+// (1 x 3 blocks of 16 x 16 MFMA outputs).  Staging and the K split are those of
+// gemm_f32 (lanes 48..63 stage right-hand sides no block reads), and every output takes
+// the same MFMA sequence, so the results are those of gemm_f32.
+constexpr int kW48 = 48;
+
+__device__ inline void finish_tile_w48(const GemmTile& t, const GemmGroup& G, const GemmCol* __restrict__ cols,
+                                       floatx4 (&acc)[3], float* red, int grp, int wq, int lane, int accumulate) {
+    __syncthreads();
+    if (grp == 1) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[((wq * 3 + j) * 4 + r) * 64 + lane] = acc[j][r];
+    }
+    __syncthreads();
+    if (grp != 0) return;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int col = t.col0 + j * 16 + (lane & 15);
+        if (col >= G.ncols) continue;
+        const GemmCol cc = cols[G.first_col + col];
+        if (!cc.ctrl[3] || cc.ctrl[1]) continue;
+        double old[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = t.m0 + wq * 16 + 4 * (lane >> 4) + r;
+            old[r] = row < G.M ? (accumulate ? cc.c[row] : cc.ceq[row]) : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = t.m0 + wq * 16 + 4 * (lane >> 4) + r;
+            const float v = acc[j][r] + red[((wq * 3 + j) * 4 + r) * 64 + lane];
+            if (row < G.M) cc.c[row] = old[r] + (double)v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(512) void gemm_f32_w48(const GemmTile* __restrict__ tiles,
+                                                    const GemmGroup* __restrict__ groups,
+                                                    const GemmCol* __restrict__ cols, int accumulate) {
+    const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const GemmGroup G = groups[t.group];
+    constexpr int LD = 80;                      // row stride: conflict-free MFMA operand reads
+    __shared__ float smem[2 * 2 * 32 * LD];     // per group: A [k][m], B [k][rhs]
+    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
+    const int lane = gt & 63, wq = gt >> 6;
+    const int lr = gt & 63, kq = (gt >> 6) * 8;
+    float* As = smem + grp * 2 * 32 * LD;
+    float* Bs = As + 32 * LD;
+    bool act;
+    const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
+    if (!__syncthreads_or(act && lr < kW48)) return;   // every right-hand side of the tile converged
+    const float* arow = (const float*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const int nk = G.ldk / 32;
+    const int nsteps = (nk + 1) / 2;            // steps per group (group 1 may idle on the last)
+    floatx4 acc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float4 ra0, ra1, rb0, rb1;
+    auto fetch = [&](int s) {
+        const int k0 = (2 * s + grp) * 32;
+        if (k0 < G.ldk) {
+            ra0 = *(const float4*)(arow + k0);
+            ra1 = *(const float4*)(arow + k0 + 4);
+            rb0 = *(const float4*)(brow + k0);
+            rb1 = *(const float4*)(brow + k0 + 4);
+        }
+    };
+    fetch(0);
+    for (int s = 0; s < nsteps; ++s) {
+        const bool valid = (2 * s + grp) < nk;
+        __syncthreads();
+        if (valid) {
+            As[(kq + 0) * LD + lr] = ra0.x; As[(kq + 1) * LD + lr] = ra0.y;
+            As[(kq + 2) * LD + lr] = ra0.z; As[(kq + 3) * LD + lr] = ra0.w;
+            As[(kq + 4) * LD + lr] = ra1.x; As[(kq + 5) * LD + lr] = ra1.y;
+            As[(kq + 6) * LD + lr] = ra1.z; As[(kq + 7) * LD + lr] = ra1.w;
+            Bs[(kq + 0) * LD + lr] = rb0.x; Bs[(kq + 1) * LD + lr] = rb0.y;
+            Bs[(kq + 2) * LD + lr] = rb0.z; Bs[(kq + 3) * LD + lr] = rb0.w;
+            Bs[(kq + 4) * LD + lr] = rb1.x; Bs[(kq + 5) * LD + lr] = rb1.y;
+            Bs[(kq + 6) * LD + lr] = rb1.z; Bs[(kq + 7) * LD + lr] = rb1.w;
+        }
+        __syncthreads();
+        if (s + 1 < nsteps) fetch(s + 1);
+        if (valid) {
+            float af[8], bf[8][3];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int kr = (4 * kk + (lane >> 4)) * LD;
+                af[kk] = As[kr + wq * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) bf[kk][j] = Bs[kr + j * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk], bf[kk][j], acc[j], 0, 0, 0);
+        }
+    }
+    finish_tile_w48(t, G, cols, acc, smem, grp, wq, lane, accumulate);
+}
+
 __device__ inline void split8(const float4& x0, const float4& x1, ushortx8& hi, ushortx8& lo) {
     const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
@@ -327,10 +433,12 @@ __global__ __launch_bounds__(256) void gemm_f64(const GemmTile* __restrict__ til
         for (int j = 0; j < 4; ++j) store_out(G, cols, t.m0 + tr + i, t.col0 + tcol + j, acc[i][j], accumulate);
 }
 
-hipError_t launch_gemm(int precision, const GemmTile* tiles, int ntiles, const GemmGroup* groups,
+hipError_t launch_gemm(int precision, int width, const GemmTile* tiles, int ntiles, const GemmGroup* groups,
                        const GemmCol* cols, int accumulate, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (precision == MATO_FP32)
+    if (precision == MATO_FP32 && width == kW48)
+        gemm_f32_w48<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
+    else if (precision == MATO_FP32)
         gemm_f32<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
     else if (precision == MATO_BF16_REFINED)
         gemm_bf16<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);

@@ -113,6 +113,24 @@ def test_large_batch_uploads_match_alone_bitwise():
         np.testing.assert_array_equal(alone.residuals(0)[0], mix.residuals(q)[0])
 
 
+def test_product_tile_widths_agree_bitwise():
+    """The FP32 inverse product over 64-column tiles (chosen for this large batch of small
+    problems) and over 48-column tiles (chosen for one problem alone) gives the same
+    coefficients bit for bit."""
+    say("product tile widths")
+    n, count = 8, 2560
+    plan = mato.Plan(n, 20, 11, 5.0, 0.3, 0.6, 1.0, "fp32")
+    scen = [sc.random_density_box(n, seed=900 + q) for q in range(count)]
+    big = mato.Batch([plan] * count, [x[0] for x in scen], [x[1] for x in scen])
+    big.step(6, use_graph=False)
+    big.sync()
+    for q in (0, 1111, count - 1):
+        alone = mato.Batch([plan], [scen[q][0]], [scen[q][1]])
+        alone.step(6, use_graph=False)
+        np.testing.assert_array_equal(alone.coeffs(0), big.coeffs(q))
+        np.testing.assert_array_equal(alone.get_state(0)["lam"], big.get_state(q)["lam"])
+
+
 def test_batch_matches_oracle_per_problem():
     say("uneven batch vs oracle")
     ns = [6, 11, 17]
