@@ -87,6 +87,10 @@ struct Recip<double> {
     static __device__ inline double rcp(double x) { return 1.0 / x; }
 };
 
+// Bit patterns, to tell an unchanged value (the sign of a zero included) from a changed one.
+__device__ inline unsigned bits_of(float x) { return __float_as_uint(x); }
+__device__ inline unsigned long long bits_of(double x) { return (unsigned long long)__double_as_longlong(x); }
+
 // One workgroup per work item: instants [t0, t0 + tc) of one problem, all pairs.
 // LDS: X [tc][3][n] (copied from the positions of the current coefficients), then
 // b_fc [tc][3][n_rows] (scalar S), then the obstacle table.  Rows after the agent
@@ -224,7 +228,15 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             S px, py, pz, dd;
             if (!shifted) {
                 const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2
-                if (q2 > 0) {
+                if (q2 > S(1.0001) && lx == 0 && ly == 0 && lzm == 0 && !dbg_d_p) {
+                    // no multiplier and clear of the collision set by a margin: 1/s < 1 (also
+                    // as the FP32 approximation), so the branch below would take w = 1 and
+                    // d e = delta, bit for bit
+                    px = dx;
+                    py = dy;
+                    pz = dz;
+                    dd = 0;                                             // unused: no d output
+                } else if (q2 > 0) {
                     const S D2 = dx * dx + dy * dy + dz * dz;
                     const S rs = Recip<S>::rsq(q2);                     // 1 / s
                     const S dl = dx * lx + dy * ly + dz * lzm;
@@ -267,9 +279,12 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
                 rmax = fmax(rmax, fn2);
                 rsum += fn2;
             }
-            __builtin_nontemporal_store(nlx, &lam[tb + p]);
-            __builtin_nontemporal_store(nly, &lam[tb + np + p]);
-            __builtin_nontemporal_store(nlz, &lam[tb + 2 * (size_t)np + p]);
+            // an iteration stores only the multipliers whose bits change: lambda = 0 on a pair
+            // that does not collide stays 0 exactly (w = 1, d e = delta, f_c = 0)
+            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) __builtin_nontemporal_store(nlx, &lam[tb + p]);
+            if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) __builtin_nontemporal_store(nly, &lam[tb + np + p]);
+            if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
+                __builtin_nontemporal_store(nlz, &lam[tb + 2 * (size_t)np + p]);
             Bt[p] = px - nlx * irho_b;
             Bt[np + p] = py - nly * irho_b;
             Bt[2 * np + p] = pz - nlz * irho_b;

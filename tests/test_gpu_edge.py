@@ -131,6 +131,29 @@ def test_product_tile_widths_agree_bitwise():
         np.testing.assert_array_equal(alone.get_state(0)["lam"], big.get_state(q)["lam"])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_far_pair_shortcut_matches_general_branch_bitwise(precision):
+    """A pair with no multiplier that clears the collision set by a margin takes a shortcut in
+    the pairwise kernel (d e = delta), and an iteration stores only the multipliers whose bits
+    change.  With the debug outputs on, every pair takes the general branch.  Both give the same
+    iterates bit for bit on a crowded scene where pairs enter and leave the collision set."""
+    say("far-pair shortcut", precision)
+    n = 24
+    plan = mato.Plan(n, 60, 11, 6.0, 0.3, 0.6, 1.0, precision)
+    s, g = sc.swap_circle(n, radius=3.0, seed=5)
+    fast, general = mato.Batch([plan], [s], [g]), mato.Batch([plan], [s], [g])
+    general.debug(True)
+    for _ in range(4):
+        fast.step(10, use_graph=False)
+        general.step(10, use_graph=False)
+        a, b = fast.get_state(0), general.get_state(0)
+        np.testing.assert_array_equal(a["lam"], b["lam"])
+        np.testing.assert_array_equal(a["c"], b["c"])
+    np.testing.assert_array_equal(fast.residuals(0)[0], general.residuals(0)[0])
+    lam = fast.get_state(0)["lam"]
+    assert 0 < np.count_nonzero(lam) < lam.size // 2      # both branches taken
+
+
 def test_batch_matches_oracle_per_problem():
     say("uneven batch vs oracle")
     ns = [6, 11, 17]
