@@ -72,6 +72,35 @@ __device__ inline void block_reduce3(T& mx, T& s1, T& s2, T* sh /* 3 * BLOCK/64 
     }
 }
 
+// Block maximum and FP64 sum, results in thread 0.  The maximum is taken in S within
+// each wavefront (exact, so the same value as in FP64); the sum in the order of
+// block_reduce3 (butterfly in each wavefront, then the wavefronts in order).
+template <typename S, int BLOCK>
+__device__ inline double block_reduce_max_sum(S mx, double& s1, double* sh /* 2 * BLOCK/64 */) {
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off));
+        s1 += __shfl_xor(s1, off);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int NW = BLOCK / 64;
+    if (lane == 0) {
+        sh[w] = (double)mx;
+        sh[NW + w] = s1;
+    }
+    __syncthreads();
+    double a = 0.0;
+    if (threadIdx.x == 0) {
+        double b = sh[NW];
+        a = sh[0];
+        for (int k = 1; k < NW; ++k) {
+            a = fmax(a, sh[k]);
+            b += sh[NW + k];
+        }
+        s1 = b;
+    }
+    return a;
+}
+
 // Fast reciprocal and reciprocal square root: the hardware approximations
 // (about 1 ulp) in FP32, exact division and square root in FP64.
 template <typename S>
@@ -132,28 +161,39 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     int pw = 64;
     while (pw < np && pw < BLOCK) pw <<= 1;
     const int tg = BLOCK / pw;
-    const int pl = tid & (pw - 1), tgid = tid / pw;
+    const int pl = tid & (pw - 1);
+    // pw >= 64: a wavefront lies in one instant group, so the group index and everything
+    // derived from it (instants, multiplier and LDS bases) are wavefront-uniform
+    const int tgid = __builtin_amdgcn_readfirstlane(tid / pw);
     const int ntl = (tgid < tc) ? (tc - tgid + tg - 1) / tg : 0;   // instants of this lane's group
     const int npb = (np + pw * U - 1) / (pw * U);                   // pair chunks
     const int nit = npb * ntl;
+    // multipliers of (chunk kc, instant ki) of this group: a uniform base and per-lane
+    // byte offsets (u pw + pl) sizeof(S) (+ np sizeof(S) per axis), all below 2^32
+    auto lam_base = [&](int kc, int ki) {
+        return (gptr<char>)(lam + ((size_t)(t0 + tgid + ki * tg) * 3 * np + (size_t)kc * pw * U));
+    };
+    const unsigned axis_bytes = (unsigned)np * sizeof(S);
 
     // staged loads of one (chunk, instant): pair codes and multipliers (or d e in set-state)
     unsigned code[U];
     S L[U][3], Q[U][3];
-    auto fetch = [&](int k) {
-        const int pb = (k / ntl) * pw * U;
-        const int tl = tgid + (k % ntl) * tg;
+    auto fetch = [&](int kc, int ki) {
+        const int pb = kc * pw * U;
+        const int tl = tgid + ki * tg;
         const size_t tb = (size_t)(t0 + tl) * 3 * np;
+        const gptr<const char> lb = lam_base(kc, ki);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = pb + u * pw + pl;
             const bool ok = p < np;
-            code[u] = ok ? pairs[p] : 0u;
+            if (ki == 0) code[u] = ok ? pairs[p] : 0u;     // the same for every instant of the chunk
             L[u][0] = L[u][1] = L[u][2] = 0;
             if (MODE != kModeInit && ok) {
-                L[u][0] = __builtin_nontemporal_load(&lam[tb + p]);
-                L[u][1] = __builtin_nontemporal_load(&lam[tb + np + p]);
-                L[u][2] = __builtin_nontemporal_load(&lam[tb + 2 * (size_t)np + p]);
+                const unsigned o = (unsigned)(u * pw + pl) * sizeof(S);
+                L[u][0] = __builtin_nontemporal_load((gptr<const S>)(lb + o));
+                L[u][1] = __builtin_nontemporal_load((gptr<const S>)(lb + o + axis_bytes));
+                L[u][2] = __builtin_nontemporal_load((gptr<const S>)(lb + o + 2 * axis_bytes));
             }
             if (MODE == kModeSetState) {
                 Q[u][0] = Q[u][1] = Q[u][2] = 0;
@@ -165,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             }
         }
     };
-    if (nit > 0) fetch(0);
+    if (nit > 0) fetch(0, 0);
 
     if (n_obs > 0) {
         gptr<const S> og = glob(Dp->obs);
@@ -180,6 +220,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     }
 
     S rmax = 0, rsum = 0;
+    int kc = 0, ki = 0;                             // chunk and instant of step k (instants inner)
     for (int k = 0; k < nit; ++k) {
         unsigned cc[U];
         S Lc[U][3], Qc[U][3];
@@ -189,10 +230,18 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             Lc[u][0] = L[u][0]; Lc[u][1] = L[u][1]; Lc[u][2] = L[u][2];
             if (MODE == kModeSetState) { Qc[u][0] = Q[u][0]; Qc[u][1] = Q[u][1]; Qc[u][2] = Q[u][2]; }
         }
-        if (k + 1 < nit) fetch(k + 1);
-        const int pb = (k / ntl) * pw * U;
-        const int tl = tgid + (k % ntl) * tg;
+        int kc1 = kc, ki1 = ki + 1;
+        if (ki1 == ntl) {
+            ki1 = 0;
+            ++kc1;
+        }
+        if (k + 1 < nit) fetch(kc1, ki1);
+        const int pb = kc * pw * U;
+        const int tl = tgid + ki * tg;
         const size_t tb = (size_t)(t0 + tl) * 3 * np;
+        const gptr<char> lb = lam_base(kc, ki);
+        kc = kc1;
+        ki = ki1;
         S* Bt = Bs + (size_t)tl * 3 * np;
         const S* X = Xs + tl * 3 * n;
 #pragma unroll
@@ -281,10 +330,12 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             }
             // an iteration stores only the multipliers whose bits change: lambda = 0 on a pair
             // that does not collide stays 0 exactly (w = 1, d e = delta, f_c = 0)
-            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) __builtin_nontemporal_store(nlx, &lam[tb + p]);
-            if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) __builtin_nontemporal_store(nly, &lam[tb + np + p]);
+            const unsigned o = (unsigned)(p - pb) * sizeof(S);
+            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) __builtin_nontemporal_store(nlx, (gptr<S>)(lb + o));
+            if (MODE != kModeIter || bits_of(nly) != bits_of(ly))
+                __builtin_nontemporal_store(nly, (gptr<S>)(lb + o + axis_bytes));
             if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
-                __builtin_nontemporal_store(nlz, &lam[tb + 2 * (size_t)np + p]);
+                __builtin_nontemporal_store(nlz, (gptr<S>)(lb + o + 2 * axis_bytes));
             Bt[p] = px - nlx * irho_b;
             Bt[np + p] = py - nly * irho_b;
             Bt[2 * np + p] = pz - nlz * irho_b;
@@ -309,11 +360,12 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         const int a = rem / n, i = rem - a * n;
         const S* Bt = Bs + ((size_t)tl * 3 + a) * np;
         S acc = 0;
-        int pj = i - 1;
+        const S* col = Bt + i - 1;          // b_ji, j < i: column i of the pair triangle
+        int off = 0;                        // row_offset(j, n) - j: the same for every lane
 #pragma unroll 8
         for (int j = 0; j < i; ++j) {
-            acc -= Bt[pj];
-            pj += n - j - 2;
+            acc -= col[off];
+            off += n - j - 2;
         }
         const S* row = Bt + row_offset(i, n) - i - 1;
 #pragma unroll 8
@@ -326,9 +378,9 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     }
 
     if (MODE == kModeIter) {
-        __shared__ double red[3 * (BLOCK / 64)];
-        double mx = (double)rmax, s1 = (double)rsum, s2 = 0.0;
-        block_reduce3<double, BLOCK>(mx, s1, s2, red);
+        __shared__ double red[2 * (BLOCK / 64)];
+        double s1 = (double)rsum;
+        const double mx = block_reduce_max_sum<S, BLOCK>(rmax, s1, red);
         if (tid == 0) {
             gptr<double> pp = part + (size_t)it.slab * 4;
             pp[0] = mx;
