@@ -120,6 +120,33 @@ struct Recip<double> {
 __device__ inline unsigned bits_of(float x) { return __float_as_uint(x); }
 __device__ inline unsigned long long bits_of(double x) { return (unsigned long long)__double_as_longlong(x); }
 
+// Multiplier access through a buffer resource: a wavefront-uniform base, a per-lane
+// 32-bit offset and a uniform one; a lane whose offset is past the resource's size
+// reads 0 and touches no memory.  Nontemporal (the multipliers are streamed once).
+constexpr int kNt = 2;
+template <typename S>
+struct Buf;
+template <>
+struct Buf<float> {
+    static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, kNt));
+    }
+    static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kNt);
+    }
+};
+template <>
+struct Buf<double> {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, kNt));
+    }
+    static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vo, so, kNt);
+    }
+};
+constexpr unsigned kOutOfRange = 0x80000000u;   // above every resource size used here
+
 // One workgroup per work item: instants [t0, t0 + tc) of one problem, all pairs.
 // LDS: X [tc][3][n] (copied from the positions of the current coefficients), then
 // b_fc [tc][3][n_rows] (scalar S), then the obstacle table.  Rows after the agent
@@ -168,12 +195,16 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     const int ntl = (tgid < tc) ? (tc - tgid + tg - 1) / tg : 0;   // instants of this lane's group
     const int npb = (np + pw * U - 1) / (pw * U);                   // pair chunks
     const int nit = npb * ntl;
-    // multipliers of (chunk kc, instant ki) of this group: a uniform base and per-lane
-    // byte offsets (u pw + pl) sizeof(S) (+ np sizeof(S) per axis), all below 2^32
-    auto lam_base = [&](int kc, int ki) {
-        return (gptr<char>)(lam + ((size_t)(t0 + tgid + ki * tg) * 3 * np + (size_t)kc * pw * U));
+    // multipliers of (chunk kc, instant ki) of this group: a buffer resource from the
+    // chunk's first pair to the end of the instant's three axes; lane offset pl sizeof(S),
+    // uniform offset (u pw + axis np) sizeof(S)
+    auto lam_rsrc = [&](int kc, int ki) {
+        const size_t first = (size_t)(t0 + tgid + ki * tg) * 3 * np + (size_t)kc * pw * U;
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(S*)(lam + first), (short)0,
+                                                 (int)((3 * np - kc * pw * U) * sizeof(S)), 0x00020000);
     };
-    const unsigned axis_bytes = (unsigned)np * sizeof(S);
+    const int axis_bytes = np * (int)sizeof(S);
+    const unsigned lane_bytes = (unsigned)pl * sizeof(S);
 
     // staged loads of one (chunk, instant): pair codes and multipliers (or d e in set-state)
     unsigned code[U];
@@ -182,18 +213,20 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         const int pb = kc * pw * U;
         const int tl = tgid + ki * tg;
         const size_t tb = (size_t)(t0 + tl) * 3 * np;
-        const gptr<const char> lb = lam_base(kc, ki);
+        const __amdgpu_buffer_rsrc_t rs = lam_rsrc(kc, ki);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = pb + u * pw + pl;
             const bool ok = p < np;
             if (ki == 0) code[u] = ok ? pairs[p] : 0u;     // the same for every instant of the chunk
-            L[u][0] = L[u][1] = L[u][2] = 0;
-            if (MODE != kModeInit && ok) {
-                const unsigned o = (unsigned)(u * pw + pl) * sizeof(S);
-                L[u][0] = __builtin_nontemporal_load((gptr<const S>)(lb + o));
-                L[u][1] = __builtin_nontemporal_load((gptr<const S>)(lb + o + axis_bytes));
-                L[u][2] = __builtin_nontemporal_load((gptr<const S>)(lb + o + 2 * axis_bytes));
+            if (MODE != kModeInit) {
+                const unsigned vo = ok ? lane_bytes : kOutOfRange;   // past the last pair: 0
+                const int so = u * pw * (int)sizeof(S);
+                L[u][0] = Buf<S>::load(rs, vo, so);
+                L[u][1] = Buf<S>::load(rs, vo, so + axis_bytes);
+                L[u][2] = Buf<S>::load(rs, vo, so + 2 * axis_bytes);
+            } else {
+                L[u][0] = L[u][1] = L[u][2] = 0;
             }
             if (MODE == kModeSetState) {
                 Q[u][0] = Q[u][1] = Q[u][2] = 0;
@@ -239,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         const int pb = kc * pw * U;
         const int tl = tgid + ki * tg;
         const size_t tb = (size_t)(t0 + tl) * 3 * np;
-        const gptr<char> lb = lam_base(kc, ki);
+        const __amdgpu_buffer_rsrc_t rs = lam_rsrc(kc, ki);
         kc = kc1;
         ki = ki1;
         S* Bt = Bs + (size_t)tl * 3 * np;
@@ -330,12 +363,11 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             }
             // an iteration stores only the multipliers whose bits change: lambda = 0 on a pair
             // that does not collide stays 0 exactly (w = 1, d e = delta, f_c = 0)
-            const unsigned o = (unsigned)(p - pb) * sizeof(S);
-            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) __builtin_nontemporal_store(nlx, (gptr<S>)(lb + o));
-            if (MODE != kModeIter || bits_of(nly) != bits_of(ly))
-                __builtin_nontemporal_store(nly, (gptr<S>)(lb + o + axis_bytes));
+            const int so = u * pw * (int)sizeof(S);
+            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) Buf<S>::store(nlx, rs, lane_bytes, so);
+            if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) Buf<S>::store(nly, rs, lane_bytes, so + axis_bytes);
             if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
-                __builtin_nontemporal_store(nlz, (gptr<S>)(lb + o + 2 * axis_bytes));
+                Buf<S>::store(nlz, rs, lane_bytes, so + 2 * axis_bytes);
             Bt[p] = px - nlx * irho_b;
             Bt[np + p] = py - nly * irho_b;
             Bt[2 * np + p] = pz - nlz * irho_b;
