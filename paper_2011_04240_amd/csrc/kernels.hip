@@ -173,6 +173,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     gptr<const S> proj_in = glob(Dp->proj_in);
     S* const dbg_proj_p = Dp->dbg_proj;
     S* const dbg_d_p = Dp->dbg_d;
+    const bool dbg_on = dbg_proj_p != nullptr || dbg_d_p != nullptr;
     gptr<double> part = glob(Dp->part);
     const S ia2 = Dp->ia2, ib2 = Dp->ib2, rho = Dp->srho, irho = Dp->sirho, lzl = Dp->lz;
     const bool shifted = Dp->shifted != 0;
@@ -307,18 +308,21 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const S dx = X[i] - xj;
             const S dy = X[n + i] - yj;
             const S dz = X[2 * n + i] - zj;
+            const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+            if (MODE == kModeIter && !shifted && !dbg_on && q2 > S(1.0001) &&
+                (bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0) {
+                // no multiplier (+0) and clear of the collision set by a margin: 1/s < 1 (also as
+                // the FP32 approximation), so the general branch would take w = 1, d e = delta,
+                // f_c = +0, lambda = +0 (unchanged, not stored), b_fc = delta and a zero
+                // residual (maximum and sum unchanged), bit for bit
+                Bt[p] = dx;
+                Bt[np + p] = dy;
+                Bt[2 * np + p] = dz;
+                continue;
+            }
             S px, py, pz, dd;
             if (!shifted) {
-                const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2
-                if (q2 > S(1.0001) && lx == 0 && ly == 0 && lzm == 0 && !dbg_d_p) {
-                    // no multiplier and clear of the collision set by a margin: 1/s < 1 (also
-                    // as the FP32 approximation), so the branch below would take w = 1 and
-                    // d e = delta, bit for bit
-                    px = dx;
-                    py = dy;
-                    pz = dz;
-                    dd = 0;                                             // unused: no d output
-                } else if (q2 > 0) {
+                if (q2 > 0) {
                     const S D2 = dx * dx + dy * dy + dz * dz;
                     const S rs = Recip<S>::rsq(q2);                     // 1 / s
                     const S dl = dx * lx + dy * ly + dz * lzm;
