@@ -196,13 +196,15 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     const int ntl = (tgid < tc) ? (tc - tgid + tg - 1) / tg : 0;   // instants of this lane's group
     const int npb = (np + pw * U - 1) / (pw * U);                   // pair chunks
     const int nit = npb * ntl;
-    // multipliers of (chunk kc, instant ki) of this group: a buffer resource from the
-    // chunk's first pair to the end of the instant's three axes; lane offset pl sizeof(S),
-    // uniform offset (u pw + axis np) sizeof(S)
-    auto lam_rsrc = [&](int kc, int ki) {
-        const size_t first = (size_t)(t0 + tgid + ki * tg) * 3 * np + (size_t)kc * pw * U;
+    // multipliers of (chunk kc, instant ki) of this group start at element
+    // first0 + kc cstride + ki istride; a buffer resource from there to the end of the
+    // instant's three axes, lane offset pl sizeof(S), uniform offset (u pw + axis np) sizeof(S)
+    const size_t first0 = (size_t)(t0 + tgid) * 3 * np;
+    const size_t istride = (size_t)tg * 3 * np;
+    const int cstride = pw * U;
+    auto rsrc_at = [&](size_t first, int kc) {
         return __builtin_amdgcn_make_buffer_rsrc((void*)(S*)(lam + first), (short)0,
-                                                 (int)((3 * np - kc * pw * U) * sizeof(S)), 0x00020000);
+                                                 (3 * np - kc * cstride) * (int)sizeof(S), 0x00020000);
     };
     const int axis_bytes = np * (int)sizeof(S);
     const unsigned lane_bytes = (unsigned)pl * sizeof(S);
@@ -210,16 +212,17 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     // staged loads of one (chunk, instant): pair codes and multipliers (or d e in set-state)
     unsigned code[U];
     S L[U][3], Q[U][3];
-    auto fetch = [&](int kc, int ki) {
-        const int pb = kc * pw * U;
-        const int tl = tgid + ki * tg;
-        const size_t tb = (size_t)(t0 + tl) * 3 * np;
-        const __amdgpu_buffer_rsrc_t rs = lam_rsrc(kc, ki);
+    auto fetch = [&](int kc, int ki, size_t first) {
+        const int pb = kc * cstride;
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(first, kc);
+        if (ki == 0) {                              // the same codes for every instant of the chunk
+#pragma unroll
+            for (int u = 0; u < U; ++u) code[u] = pairs[min(pb + u * pw + pl, np - 1)];   // past np: unused
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = pb + u * pw + pl;
             const bool ok = p < np;
-            if (ki == 0) code[u] = ok ? pairs[p] : 0u;     // the same for every instant of the chunk
             if (MODE != kModeInit) {
                 const unsigned vo = ok ? lane_bytes : kOutOfRange;   // past the last pair: 0
                 const int so = u * pw * (int)sizeof(S);
@@ -232,14 +235,15 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             if (MODE == kModeSetState) {
                 Q[u][0] = Q[u][1] = Q[u][2] = 0;
                 if (ok) {
-                    Q[u][0] = proj_in[tb + p];
-                    Q[u][1] = proj_in[tb + np + p];
-                    Q[u][2] = proj_in[tb + 2 * (size_t)np + p];
+                    const size_t e = first + (size_t)(u * pw + pl);
+                    Q[u][0] = proj_in[e];
+                    Q[u][1] = proj_in[e + np];
+                    Q[u][2] = proj_in[e + 2 * (size_t)np];
                 }
             }
         }
     };
-    if (nit > 0) fetch(0, 0);
+    if (nit > 0) fetch(0, 0, first0);
 
     if (n_obs > 0) {
         gptr<const S> og = glob(Dp->obs);
@@ -255,6 +259,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
 
     S rmax = 0, rsum = 0;
     int kc = 0, ki = 0;                             // chunk and instant of step k (instants inner)
+    size_t f_cur = first0, c_first = first0;        // first multiplier of (kc, ki) and of (kc, 0)
     for (int k = 0; k < nit; ++k) {
         unsigned cc[U];
         S Lc[U][3], Qc[U][3];
@@ -265,18 +270,23 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             if (MODE == kModeSetState) { Qc[u][0] = Q[u][0]; Qc[u][1] = Q[u][1]; Qc[u][2] = Q[u][2]; }
         }
         int kc1 = kc, ki1 = ki + 1;
+        size_t f_nxt = f_cur + istride, c_nxt = c_first;
         if (ki1 == ntl) {
             ki1 = 0;
             ++kc1;
+            c_nxt = c_first + cstride;
+            f_nxt = c_nxt;
         }
-        if (k + 1 < nit) fetch(kc1, ki1);
-        const int pb = kc * pw * U;
+        if (k + 1 < nit) fetch(kc1, ki1, f_nxt);
+        const int pb = kc * cstride;
         const int tl = tgid + ki * tg;
-        const size_t tb = (size_t)(t0 + tl) * 3 * np;
-        const __amdgpu_buffer_rsrc_t rs = lam_rsrc(kc, ki);
+        const size_t fc = f_cur;                    // element (t0 + tl) 3 np + pb
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(f_cur, kc);
         kc = kc1;
         ki = ki1;
-        S* Bt = Bs + (size_t)tl * 3 * np;
+        f_cur = f_nxt;
+        c_first = c_nxt;
+        S* Bt = Bs + tl * 3 * np;
         const S* X = Xs + tl * 3 * n;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -309,8 +319,10 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const S dy = X[n + i] - yj;
             const S dz = X[2 * n + i] - zj;
             const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
-            if (MODE == kModeIter && !shifted && !dbg_on && q2 > S(1.0001) &&
-                (bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0) {
+            // (bitwise and: one condition, not a chain of branches)
+            const bool fast = (MODE == kModeIter) & !shifted & !dbg_on & (q2 > S(1.0001)) &
+                              ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0);
+            if (fast) {
                 // no multiplier (+0) and clear of the collision set by a margin: 1/s < 1 (also as
                 // the FP32 approximation), so the general branch would take w = 1, d e = delta,
                 // f_c = +0, lambda = +0 (unchanged, not stored), b_fc = delta and a zero
@@ -375,13 +387,16 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             Bt[p] = px - nlx * irho_b;
             Bt[np + p] = py - nly * irho_b;
             Bt[2 * np + p] = pz - nlz * irho_b;
-            if (dbg_proj_p) {
-                gptr<S> dp = glob(dbg_proj_p);
-                dp[tb + p] = px;
-                dp[tb + np + p] = py;
-                dp[tb + 2 * (size_t)np + p] = pz;
+            if (dbg_on) {
+                const size_t e = fc + (size_t)(u * pw + pl);          // (t0 + tl) 3 np + p
+                if (dbg_proj_p) {
+                    gptr<S> dp = glob(dbg_proj_p);
+                    dp[e] = px;
+                    dp[e + np] = py;
+                    dp[e + 2 * (size_t)np] = pz;
+                }
+                if (dbg_d_p) glob(dbg_d_p)[(size_t)(t0 + tl) * np + p] = dd;
             }
-            if (dbg_d_p) glob(dbg_d_p)[(size_t)(t0 + tl) * np + p] = dd;
         }
     }
     __syncthreads();
