@@ -311,10 +311,11 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     ctrl[3] = 1;
     ctrl[4] = 0;
     MATO_HIP(hipMemcpy(B->dctrl + kCtrl * q, ctrl, sizeof(ctrl), hipMemcpyHostToDevice));
+    // positions of the new coefficients first: the pairwise pass measures b_fc against them
+    if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->common_nv(), true,
                                 B->stream));
     MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
-    if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(hipStreamSynchronize(B->stream));
     return MATO_OK;
 }

@@ -357,7 +357,7 @@ struct Engine {
     void slot_items(int q, std::vector<WorkItem>& out, size_t* maxlds, int as_prob) {
         Prob& P = probs[q];
         const int cap = device_lds_limit() - 1024;   // room for the kernel's static reduction buffer
-        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S);
+        const size_t per_t = pairwise_lds_per_instant(P);
         const size_t fixed = (size_t)kObs * P.n_obs * sizeof(S);
         int tc = std::max(1, items_per_wg / std::max(1, P.np));
         tc = std::min(tc, P.T);
@@ -374,8 +374,15 @@ struct Engine {
         }
     }
 
+    // LDS of the pairwise kernel per instant of a work item: the FP64 sum over agents of X,
+    // positions X and b_fc (or its corrections) and two flag words per 32 pairs
+    static size_t pairwise_lds_per_instant(const Prob& P) {
+        return (size_t)3 * sizeof(double) + (size_t)3 * (P.n + P.np) * sizeof(S) +
+               (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
+    }
+
     mato_status check_lds(const Prob& P) const {
-        const size_t per_t = (size_t)3 * (P.n + P.np) * sizeof(S) + (size_t)kObs * P.n_obs * sizeof(S);
+        const size_t per_t = pairwise_lds_per_instant(P) + (size_t)kObs * P.n_obs * sizeof(S);
         if (per_t > (size_t)(device_lds_limit() - 1024)) {
             set_error("n = %d, n_obs = %d needs %zu bytes of LDS per instant, device allows %d", P.n, P.n_obs,
                       per_t, device_lds_limit() - 1024);

@@ -116,6 +116,14 @@ struct Recip<double> {
     static __device__ inline double rcp(double x) { return 1.0 / x; }
 };
 
+// hi + lo += v with the rounding error of hi + v kept in lo (Knuth's TwoSum: error-free,
+// and the same bits for either order of the two summands).
+__device__ inline void two_sum_add(double& hi, double& lo, double v) {
+    const double s = hi + v, bv = s - hi;
+    lo += (hi - (s - bv)) + (v - bv);
+    hi = s;
+}
+
 // Bit patterns, to tell an unchanged value (the sign of a zero included) from a changed one.
 __device__ inline unsigned bits_of(float x) { return __float_as_uint(x); }
 __device__ inline unsigned long long bits_of(double x) { return (unsigned long long)__double_as_longlong(x); }
@@ -181,9 +189,20 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     const S irho_b = (MODE == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->sirho_next : irho;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    S* Xs = reinterpret_cast<S*>(smem_raw);
+    double* SXs = reinterpret_cast<double*>(smem_raw);   // [tc][3] sum over agents of X (sum form)
+    S* Xs = reinterpret_cast<S*>(SXs + tc * 3);
     S* Bs = Xs + tc * 3 * n;
     S* Os = Bs + (size_t)tc * 3 * np;                // obstacle table [n_obs][kObs]
+    // sum form of the per-agent sums (plain iteration without obstacles):
+    //   S_i = n X_i - sum_j X_j + sum over pairs of i whose b_fc is not delta of (b_fc - delta),
+    // the corrections in Bs, flagged by pair in row order (Mr) and in column order (Mc).  The
+    // agent sum is compensated and S_i is formed in FP64 and rounded once: a rounding of
+    // sum_j X_j shared by every agent would shift the agent mean of S, which the x-step's
+    // mean block (no rho term) amplifies
+    const bool sumform = (MODE == kModeIter || MODE == kModeSetState) && !shifted && n_obs == 0;
+    const int nw = (np + 31) >> 5;
+    unsigned* Mr = reinterpret_cast<unsigned*>(Os + (size_t)n_obs * kObs);   // [tc][nw]
+    unsigned* Mc = Mr + tc * nw;                                              // [tc][nw]
     const int tid = threadIdx.x;
 
     int pw = 64;
@@ -249,12 +268,27 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         gptr<const S> og = glob(Dp->obs);
         for (int idx = tid; idx < n_obs * kObs; idx += BLOCK) Os[idx] = og[idx];
     }
-    if (MODE != kModeSetState) {
+    if (MODE != kModeSetState || sumform) {
         // positions of the block's instants: one contiguous slab of X [t][3][n]
         const int nX = tc * 3 * n;
         gptr<const S> Xg = Xm + (size_t)t0 * 3 * n;
         for (int idx = tid; idx < nX; idx += BLOCK) Xs[idx] = Xg[idx];
+        if (sumform)
+            for (int idx = tid; idx < 2 * tc * nw; idx += BLOCK) Mr[idx] = 0u;
         __syncthreads();
+        if (sumform) {                              // sum_j X_j of each (instant, axis) row: one
+            const int lane = tid & 63;              // wavefront per row, double-double (TwoSum), a
+            for (int r = tid >> 6; r < tc * 3; r += BLOCK / 64) {   // fixed butterfly order
+                double hi = 0.0, lo = 0.0;
+                for (int j = lane; j < n; j += 64) two_sum_add(hi, lo, (double)Xs[r * n + j]);
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double h2 = __shfl_xor(hi, off), l2 = __shfl_xor(lo, off);
+                    two_sum_add(hi, lo, h2);        // exact and symmetric: every lane gets the same bits
+                    lo += l2;
+                }
+                if (lane == 0) SXs[r] = hi + lo;
+            }
+        }
     }
 
     S rmax = 0, rsum = 0;
@@ -293,13 +327,29 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const int p = pb + u * pw + pl;
             if (p >= np) continue;
             const S lx = Lc[u][0], ly = Lc[u][1], lzm = Lc[u][2];
+            const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
+            // sum form: a pair whose b_fc - delta is not +0 on every axis keeps it in Bt and is
+            // flagged (the flags and values depend only on the state, in every mode)
+            auto record = [&](S cx, S cy, S cz) {
+                if ((bits_of(cx) | bits_of(cy) | bits_of(cz)) == 0) return;
+                Bt[p] = cx;
+                Bt[np + p] = cy;
+                Bt[2 * np + p] = cz;
+                const int c = j * (j - 1) / 2 + i;  // column order: pairs grouped by the larger agent
+                atomicOr(&Mr[tl * nw + (p >> 5)], 1u << (p & 31));
+                atomicOr(&Mc[tl * nw + (c >> 5)], 1u << (c & 31));
+            };
             if (MODE == kModeSetState) {
-                Bt[p] = Qc[u][0] - lx * irho;
-                Bt[np + p] = Qc[u][1] - ly * irho;
-                Bt[2 * np + p] = Qc[u][2] - lzm * irho;
+                const S bx = Qc[u][0] - lx * irho, by = Qc[u][1] - ly * irho, bz = Qc[u][2] - lzm * irho;
+                if (sumform) {
+                    record(bx - (X[i] - X[j]), by - (X[n + i] - X[n + j]), bz - (X[2 * n + i] - X[2 * n + j]));
+                } else {
+                    Bt[p] = bx;
+                    Bt[np + p] = by;
+                    Bt[2 * np + p] = bz;
+                }
                 continue;
             }
-            const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
             // partner: agent j, or (rows after the pairs) static obstacle j - n with its own axes
             S xj, yj, zj, ia2p = ia2, ib2p = ib2, lzp = lzl;
             if (!OBS || j < n) {
@@ -319,17 +369,19 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             const S dy = X[n + i] - yj;
             const S dz = X[2 * n + i] - zj;
             const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+            // no multiplier (+0) and clear of the collision set by a margin: 1/s < 1 (also as the
+            // FP32 approximation), so the general branch takes w = 1, d e = delta, f_c = +0,
+            // lambda = +0 (unchanged, not stored), b_fc = delta and a zero residual (maximum and
+            // sum unchanged), bit for bit; the shortcut below does just that
             // (bitwise and: one condition, not a chain of branches)
-            const bool fast = (MODE == kModeIter) & !shifted & !dbg_on & (q2 > S(1.0001)) &
-                              ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0);
+            const bool clear = (q2 > S(1.0001)) & ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0);
+            const bool fast = (MODE == kModeIter) & !shifted & !dbg_on & clear;
             if (fast) {
-                // no multiplier (+0) and clear of the collision set by a margin: 1/s < 1 (also as
-                // the FP32 approximation), so the general branch would take w = 1, d e = delta,
-                // f_c = +0, lambda = +0 (unchanged, not stored), b_fc = delta and a zero
-                // residual (maximum and sum unchanged), bit for bit
-                Bt[p] = dx;
-                Bt[np + p] = dy;
-                Bt[2 * np + p] = dz;
+                if (!sumform) {                     // the sum form needs no entry for b_fc = delta
+                    Bt[p] = dx;
+                    Bt[np + p] = dy;
+                    Bt[2 * np + p] = dz;
+                }
                 continue;
             }
             S px, py, pz, dd;
@@ -384,9 +436,14 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
             if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) Buf<S>::store(nly, rs, lane_bytes, so + axis_bytes);
             if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
                 Buf<S>::store(nlz, rs, lane_bytes, so + 2 * axis_bytes);
-            Bt[p] = px - nlx * irho_b;
-            Bt[np + p] = py - nly * irho_b;
-            Bt[2 * np + p] = pz - nlz * irho_b;
+            const S bx = px - nlx * irho_b, by = py - nly * irho_b, bz = pz - nlz * irho_b;
+            if (!sumform) {
+                Bt[p] = bx;
+                Bt[np + p] = by;
+                Bt[2 * np + p] = bz;
+            } else {
+                record(bx - dx, by - dy, bz - dz);   // +0 for a clear pair (b_fc = delta)
+            }
             if (dbg_on) {
                 const size_t e = fc + (size_t)(u * pw + pl);          // (t0 + tl) 3 np + p
                 if (dbg_proj_p) {
@@ -402,7 +459,9 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     __syncthreads();
 
     // S_i(t) = sum_{j<i} (-b_ji) + sum_{j>i} b_ij, j ascending (fixed order), then
-    // sum_o (x_o + b_io) over static obstacles, o ascending
+    // sum_o (x_o + b_io) over static obstacles, o ascending.  Sum form: n X_i - sum_j X_j,
+    // then the corrections of the flagged pairs (j, i), j < i ascending, and (i, j), j > i
+    // ascending (b_fc = delta + correction, and sum_{j != i} (X_i - X_j) = n X_i - sum_j X_j)
     const int n3 = 3 * n;
     const int nS = tc * n3;
     for (int o = tid; o < nS; o += BLOCK) {
@@ -410,6 +469,30 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         const int rem = o - tl * n3;
         const int a = rem / n, i = rem - a * n;
         const S* Bt = Bs + ((size_t)tl * 3 + a) * np;
+        if (sumform) {
+            double acc = (double)n * (double)Xs[((size_t)tl * 3 + a) * n + i] - SXs[tl * 3 + a];
+            // flagged bits of [lo, hi) in word w, ascending
+            auto each_bit = [&](const unsigned* m, int lo, int hi, auto&& f) {
+                for (int w = lo >> 5; lo < hi && w <= (hi - 1) >> 5; ++w) {
+                    unsigned bits = m[w];
+                    if (lo > 32 * w) bits &= ~0u << (lo - 32 * w);
+                    if (hi - 32 * w < 32) bits &= (1u << (hi - 32 * w)) - 1u;
+                    while (bits) {
+                        f(32 * w + __builtin_ctz(bits));
+                        bits &= bits - 1u;
+                    }
+                }
+            };
+            const int c0 = i * (i - 1) / 2;         // pairs (j, i), j < i: column bits c0 + j
+            each_bit(Mc + tl * nw, c0, c0 + i, [&](int c) {
+                const int j = c - c0;
+                acc -= (double)Bt[row_offset(j, n) + i - j - 1];
+            });
+            const int r0 = row_offset(i, n);        // pairs (i, j), j > i: row bits r0 + j - i - 1
+            each_bit(Mr + tl * nw, r0, r0 + n - i - 1, [&](int p) { acc += (double)Bt[p]; });
+            ssum[((size_t)(t0 + tl) * 3 + a) * n + i] = (S)acc;
+            continue;
+        }
         S acc = 0;
         const S* col = Bt + i - 1;          // b_ji, j < i: column i of the pair triangle
         int off = 0;                        // row_offset(j, n) - j: the same for every lane
