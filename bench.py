@@ -9,8 +9,10 @@ stepped together (one batch's pairwise stage beside the other's per-problem
 kernels); the step as one batch on one stream is the default.
 
 Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step),
-the roofline of the pairwise kernel (24 algorithmic bytes per pair-instant:
-the FP32 multipliers read and written), timed with HIP events on the stream of
+the roofline of the pairwise kernel (12 algorithmic bytes per pair-instant: the
+FP32 multipliers read; a multiplier is written back only where its value changes,
+which is rare: 24 bytes per pair-instant, every multiplier read and written back,
+is reported beside it), timed with HIP events on the stream of
 the single batch of all B problems, and the FP64 oracle timed on the host on a
 bounded sample.  Also in the
 line: the same step with the structured x/y/z solve, served p50/p99 solve latency
@@ -32,7 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 24            # FP32 lambda: 12 B read + 12 B written per pair-instant
+BYTES_PER_UPDATE = 12            # FP32 lambda read per pair-instant (written back only where it changes)
+METHOD_BYTES_PER_UPDATE = 24     # every multiplier read and written back, as the method states the step
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "pairwise_n64_T100_B1024_counters.txt")
 
 
@@ -483,16 +486,18 @@ def mixed_batching(count=256, iters=30, seed=0):
 
 
 def stream_ceiling(nbytes, probe="copy"):
-    """Best rate of the library's streaming copy, or of its in-place streaming update (equal
-    HBM reads and writes, at the same addresses: the multipliers' pattern), over a few grid
-    sizes, for `nbytes` each way: the practical ceilings of the multiplier stream."""
+    """Best rate of the library's streaming copy, its in-place streaming update (equal HBM
+    reads and writes at the same addresses) or its streaming read, over a few grid sizes, for
+    `nbytes` read (and as many written by the copy and the update): the practical ceilings of
+    the multiplier stream."""
     from paper_2011_04240_amd import mato
-    fn = mato.mato_stream_copy if probe == "copy" else mato.mato_stream_update
+    fn = {"copy": mato.mato_stream_copy, "update": mato.mato_stream_update, "read": mato.mato_stream_read}[probe]
+    moved = 1 if probe == "read" else 2
     nbytes -= nbytes % 16
     best = None
     for grid in (1024, 2048, 4096, 16384, 65536):
         ms = fn(nbytes, grid, 10)
-        gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+        gbs = moved * nbytes / (ms * 1e-3) / 1e9
         if best is None or gbs > best[0]:
             best = (gbs, grid, ms)
     return {"GBps": best[0], "grid": best[1], "ms_per_pass": best[2], "bytes_each_way": nbytes}
@@ -575,10 +580,12 @@ def run_main(args, pool):
     pw_avg_s = pw_ms / max(launches, 1) / 1e3
     alg_bytes = BYTES_PER_UPDATE * npairs * T * B
     achieved = alg_bytes / pw_avg_s / 1e9
+    method_bytes = METHOD_BYTES_PER_UPDATE * npairs * T * B
     traffic = traffic_from_counters() if (n, T, B) == (64, 100, 1024) else None
     batch.timing(False)
-    stream = stream_ceiling(alg_bytes // 2)
-    stream_upd = stream_ceiling(alg_bytes // 2, "update")
+    stream_rd = stream_ceiling(alg_bytes, "read")
+    stream = stream_ceiling(alg_bytes)
+    stream_upd = stream_ceiling(alg_bytes, "update")
     r_max, _, _ = batch.residuals(0)
     batch.close()
     single = {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": value}
@@ -610,8 +617,10 @@ def run_main(args, pool):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "stream_copy": stream, "frac_of_stream_copy": achieved / stream["GBps"],
-                     "stream_update": stream_upd, "frac_of_stream_update": achieved / stream_upd["GBps"]},
+                     "stream_read": stream_rd, "frac_of_stream_read": achieved / stream_rd["GBps"],
+                     "method_bytes_per_launch": method_bytes,
+                     "method_GBps": method_bytes / pw_avg_s / 1e9,
+                     "stream_copy": stream, "stream_update": stream_upd},
         "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
         "single_stream": single,
     }

@@ -382,6 +382,14 @@ mato_status mato_stream_copy(int64_t bytes, int32_t grid, int32_t iters, void* h
  * one pass.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (also on a wrong value). */
 mato_status mato_stream_update(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream, double* ms_per_update);
 
+/* Not part of the method: as mato_stream_copy for a pure read of one buffer of `bytes`
+ * (every float 1.0; 16-byte nontemporal loads; each workgroup writes one partial sum,
+ * which the host checks: exact while a workgroup reads at most 2^24 floats, else
+ * INVALID_ARG).  Writes the mean time of one pass: the practical ceiling of the
+ * pairwise stage's multiplier stream once unchanged multipliers are not written back.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (also on a wrong sum). */
+mato_status mato_stream_read(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream, double* ms_per_read);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,8 +1,8 @@
-// Measurement utilities of libmato: a streaming copy and a streaming in-place update
-// (equal HBM reads and writes, 16-byte nontemporal accesses, grid-stride), the
-// practical ceilings against which the pairwise stage's multiplier stream (12 bytes
-// read and 12 written back in place per pair-instant) is compared.  Not part of the
-// method.
+// Measurement utilities of libmato: a streaming copy, a streaming in-place update
+// (equal HBM reads and writes) and a streaming read (16-byte nontemporal accesses,
+// grid-stride), the practical ceilings against which the pairwise stage's multiplier
+// stream (12 bytes read per pair-instant; written back only where a multiplier changes)
+// is compared.  Not part of the method.
 #include "common.h"
 
 #include <algorithm>
@@ -22,6 +22,25 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(const v4f* __restrict_
 __global__ __launch_bounds__(256) void stream_update_kernel(v4f* __restrict__ x, size_t n4) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
         __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) * 0.5f + 1.0f, x + i);
+}
+
+// Sum of the floats each workgroup reads (one partial per workgroup, so that the loads
+// stay); with every float 1.0 and at most 2^24 per workgroup the sums are exact.
+__global__ __launch_bounds__(256) void stream_read_kernel(const v4f* __restrict__ src, size_t n4,
+                                                          float* __restrict__ part) {
+    __shared__ float red[256];
+    float acc = 0.0f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        const v4f v = __builtin_nontemporal_load(src + i);
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 }  // namespace mato
@@ -120,5 +139,56 @@ extern "C" mato_status mato_stream_update(int64_t bytes, int32_t grid, int32_t i
     if (e1) (void)hipEventDestroy(e1);
     dfree(x);
     if (status == MATO_OK) *ms_per_update = (double)ms / iters;
+    return status;
+}
+
+extern "C" mato_status mato_stream_read(int64_t bytes, int32_t grid, int32_t iters, void* hip_stream,
+                                        double* ms_per_read) {
+    if (!ms_per_read || bytes < 16 || bytes % 16 != 0 || grid < 1 || iters < 1) {
+        set_error("stream read: bytes a positive multiple of 16, grid and iters >= 1");
+        return MATO_ERR_INVALID_ARG;
+    }
+    const size_t n4 = (size_t)bytes / 16;
+    if (n4 > ((size_t)grid << 22)) {                // at most 2^24 floats per workgroup: exact sums
+        set_error("stream read: more than 2^24 floats per workgroup; use a larger grid");
+        return MATO_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    void* src = nullptr;
+    float* part = nullptr;
+    if (hipMalloc(&src, (size_t)bytes) != hipSuccess || hipMalloc(&part, sizeof(float) * grid) != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(src);
+        set_error("device allocation of %lld bytes failed", (long long)bytes);
+        return MATO_ERR_OUT_OF_MEMORY;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.0f;
+    std::vector<float> hp(grid);
+    auto run = [&]() -> mato_status {
+        MATO_HIP(hipMemsetD32Async((hipDeviceptr_t)src, 0x3f800000, n4 * 4, st));   // every float 1.0
+        MATO_HIP(hipEventCreate(&e0));
+        MATO_HIP(hipEventCreate(&e1));
+        stream_read_kernel<<<grid, 256, 0, st>>>((const v4f*)src, n4, part);   // warm-up
+        MATO_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < iters; ++r) stream_read_kernel<<<grid, 256, 0, st>>>((const v4f*)src, n4, part);
+        MATO_HIP(hipEventRecord(e1, st));
+        MATO_HIP(hipEventSynchronize(e1));
+        MATO_HIP(hipEventElapsedTime(&ms, e0, e1));
+        MATO_HIP(hipMemcpy(hp.data(), part, sizeof(float) * grid, hipMemcpyDeviceToHost));
+        double total = 0.0;
+        for (float v : hp) total += v;
+        if (total != (double)n4 * 4) {
+            set_error("stream read: read %.0f floats of 1.0, expected %zu", total, n4 * 4);
+            return MATO_ERR_HIP;
+        }
+        return MATO_OK;
+    };
+    const mato_status status = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(src);
+    dfree(part);
+    if (status == MATO_OK) *ms_per_read = (double)ms / iters;
     return status;
 }

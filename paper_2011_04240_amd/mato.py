@@ -115,6 +115,7 @@ SIGNATURES = {
     "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
     "mato_stream_copy": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
     "mato_stream_update": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
+    "mato_stream_read": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
     "mato_stream_create": (_i32, [_pvp]),
     "mato_stream_destroy": (_i32, [_vp]),
 }
@@ -441,6 +442,12 @@ def mato_stream_copy(nbytes, grid=1024, iters=10, stream=None):
 def mato_stream_update(nbytes, grid=1024, iters=10, stream=None):
     ms = _f64()
     _check(lib().mato_stream_update(nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def mato_stream_read(nbytes, grid=1024, iters=10, stream=None):
+    ms = _f64()
+    _check(lib().mato_stream_read(nbytes, grid, iters, _stream_ptr(stream), ctypes.byref(ms)))
     return ms.value
 
 

@@ -300,6 +300,12 @@ def test_stream_copy_probe():
     with pytest.raises(mato.MatoError) as e:
         mato.mato_stream_update(1 << 24, 0, 1)
     assert e.value.status == mato.MATO_ERR_INVALID_ARG
+    ms = mato.mato_stream_read(1 << 24, 256, 3)          # checks the sum of what it read
+    assert ms > 0
+    assert mato.mato_stream_read(1 << 24, 1, 1) > 0      # 2^22 floats on one workgroup: exact
+    with pytest.raises(mato.MatoError) as e:
+        mato.mato_stream_read(1 << 30, 1, 1)              # 2^28 floats on one workgroup: refused
+    assert e.value.status == mato.MATO_ERR_INVALID_ARG
 
 
 def test_batches_on_library_streams():
