@@ -276,17 +276,19 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
         if (sumform)
             for (int idx = tid; idx < 2 * tc * nw; idx += BLOCK) Mr[idx] = 0u;
         __syncthreads();
-        if (sumform) {                              // sum_j X_j of each (instant, axis) row: one
-            const int lane = tid & 63;              // wavefront per row, double-double (TwoSum), a
-            for (int r = tid >> 6; r < tc * 3; r += BLOCK / 64) {   // fixed butterfly order
+        if (sumform) {                              // sum_j X_j of each (instant, axis) row:
+            int G = 1;                              // G = min(64, 2^ceil(log2 n)) lanes per row (a
+            while (G < n && G < 64) G <<= 1;        // function of n only), lane-strided double-double
+            const int seg = tid / G, sl = tid & (G - 1);   // sums (TwoSum), then a butterfly within
+            for (int r = seg; r < tc * 3; r += BLOCK / G) { // the segment: a fixed order
                 double hi = 0.0, lo = 0.0;
-                for (int j = lane; j < n; j += 64) two_sum_add(hi, lo, (double)Xs[r * n + j]);
-                for (int off = 32; off > 0; off >>= 1) {
+                for (int j = sl; j < n; j += G) two_sum_add(hi, lo, (double)Xs[r * n + j]);
+                for (int off = G >> 1; off > 0; off >>= 1) {
                     const double h2 = __shfl_xor(hi, off), l2 = __shfl_xor(lo, off);
                     two_sum_add(hi, lo, h2);        // exact and symmetric: every lane gets the same bits
                     lo += l2;
                 }
-                if (lane == 0) SXs[r] = hi + lo;
+                if (sl == 0) SXs[r] = (hi + lo) + 0.0;   // + 0.0: a -0 total as +0
             }
         }
     }
