@@ -156,9 +156,11 @@ struct Buf<double> {
 constexpr unsigned kOutOfRange = 0x80000000u;   // above every resource size used here
 
 // One workgroup per work item: instants [t0, t0 + tc) of one problem, all pairs.
-// LDS: X [tc][3][n] (copied from the positions of the current coefficients), then
-// b_fc [tc][3][n_rows] (scalar S), then the obstacle table.  Rows after the agent
-// pairs pair an agent with a static obstacle (fixed centre, own semi-axes).
+// LDS: the FP64 agent sums of X [tc][3] (sum form), X [tc][3][n] (copied from the
+// positions of the current coefficients), b_fc [tc][3][n_rows] (scalar S; in the sum
+// form only the corrections of flagged pairs), the obstacle table, then the row- and
+// column-ordered pair flags [tc][ceil(n_rows / 32)] each.  Rows after the agent pairs
+// pair an agent with a static obstacle (fixed centre, own semi-axes).
 // Threads form `tg` instant groups of `pw` pair lanes (pw = the smallest power of two
 // >= n_pairs, between 64 and BLOCK).  A lane owns U pairs of a chunk and walks its
 // group's instants; the multipliers of the next (chunk, instant) are loaded while the
