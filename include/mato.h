@@ -296,7 +296,9 @@ void        mato_server_destroy(mato_server s);
 mato_status mato_server_warm(mato_server s, int32_t n_min, int32_t n_max);
 
 /* Queues one problem (n agents; starts/goals [n][3], copied).  *id identifies it.
- * Errors: INVALID_ARG, UNSUPPORTED (n > MATO_MAX_AGENTS), NONFINITE. */
+ * Errors: INVALID_ARG, UNSUPPORTED (n > MATO_MAX_AGENTS, or a pairwise stage that does not
+ * fit the device), NONFINITE.  A queued request that still cannot be started (its slot
+ * set-up fails) is rejected by mato_server_step, as described there. */
 mato_status mato_server_submit(mato_server s, int32_t n, const double* starts, const double* goals,
                                int64_t* id);
 
@@ -309,8 +311,9 @@ mato_status mato_server_submit_ex(mato_server s, int32_t n, const double* starts
 /* One scheduling step: retire finished problems, admit queued ones, run `chunk`
  * iterations of the resident problems (asynchronously).  Reports resident and
  * queued counts after admission.  A request that can never run is rejected here
- * instead of holding up the queue: its plan could not be built, or with nothing
- * resident the budget still cannot hold its plans and state. */
+ * instead of holding up the queue: its plan could not be built, its slot could not be
+ * set up (any error but HIP, which is returned), or with nothing resident the budget
+ * still cannot hold its plans and state. */
 mato_status mato_server_step(mato_server s, int32_t* running, int32_t* queued);
 
 /* state: 0 queued, 1 resident, 2 finished, 3 rejected; iterations taken, converged

@@ -381,7 +381,7 @@ struct Engine {
                (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
     }
 
-    mato_status check_lds(const Prob& P) const {
+    static mato_status check_lds(const Prob& P) {
         const size_t per_t = pairwise_lds_per_instant(P) + (size_t)kObs * P.n_obs * sizeof(S);
         if (per_t > (size_t)(device_lds_limit() - 1024)) {
             set_error("n = %d, n_obs = %d needs %zu bytes of LDS per instant, device allows %d", P.n, P.n_obs,

@@ -242,8 +242,17 @@ struct ServerOps {
             }
             e->probs[q].iter_cap = s->cfg.max_iters;
             e->probs[q].shifted = s->cfg.projection;
-            MATO_TRY(e->attach(q, plan, R.starts.data(), R.goals.data(), nullptr,
-                               R.n_obs > 0 ? R.obstacles.data() : nullptr));
+            const mato_status ast = e->attach(q, plan, R.starts.data(), R.goals.data(), nullptr,
+                                              R.n_obs > 0 ? R.obstacles.data() : nullptr);
+            if (ast == MATO_ERR_HIP) return ast;                // the device itself failed
+            if (ast != MATO_OK) {
+                // this request cannot run here (e.g. its pairwise stage does not fit the
+                // device): it leaves the queue, and the requests behind it are served
+                e->probs[q].active = false;
+                e->lists_dirty = true;
+                reject(s, ast, last_error());
+                continue;
+            }
             e->probs[q].stages.clear();
             e->probs[q].stage_start.clear();
             if (s->cfg.rho_stages > 0)
@@ -289,6 +298,15 @@ struct ServerOps {
         MATO_TRY(e->upload_desc());            // every slot starts inactive with valid control words
         s->slot_req.assign(s->cfg.max_slots, -1);
         return MATO_OK;
+    }
+
+    // UNSUPPORTED if the pairwise stage of an (n, n_obs) problem does not fit the device
+    static mato_status check_size(int n, int n_obs) {
+        typename Engine<S>::Prob P;
+        P.n = n;
+        P.n_obs = n_obs;
+        P.np = n * (n - 1) / 2 + n * n_obs;
+        return Engine<S>::check_lds(P);
     }
 
     static void destroy(mato_server s) { delete E(s); }
@@ -371,6 +389,7 @@ extern "C" mato_status mato_server_submit_ex(mato_server s, int32_t n, const dou
         set_error("n_obs = %d outside 0..%d", n_obs, MATO_MAX_OBSTACLES);
         return MATO_ERR_INVALID_ARG;
     }
+    MATO_TRY(sdispatch(s, [&](auto ops) { return ops.check_size(n, n_obs); }));
     mato_server_s::Req R;
     R.n = n;
     R.n_obs = n_obs;
