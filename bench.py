@@ -34,9 +34,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 12            # FP32 lambda read per pair-instant (written back only where it changes)
-METHOD_BYTES_PER_UPDATE = 24     # every multiplier read and written back, as the method states the step
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "pairwise_n64_T100_B1024_counters.txt")
+BYTES_PER_UPDATE = 24            # every FP32 multiplier read and written back, as the method states the step
+READ_BYTES_PER_UPDATE = 12       # the multiplier reads alone (the kernel writes a multiplier only where it changes)
+PROFILES = os.path.join(ROOT, "profiles")
+
+# workloads of the pairwise stage: name -> (description, n, problems per launch, generator(n, seed))
+WORKLOADS = {
+    "box": ("random-box problems (uniform in 10 x 10 x 5 m, >= 1 m apart)", 64, 1024, "random_box"),
+    "crowded": ("antipodal swaps through a 2 m sphere (Fibonacci lattice, +-0.05 m jitter)", 64, 1024, "swap_sphere"),
+    "packed": ("starts and goals packed in a 0.2 m cube: every pair overlaps", 64, 1024, "packed_cube"),
+    "box128": ("random-box problems at the n = 64 density (2:2:1 box)", 128, 256, "random_density_box"),
+}
+
+
+def workload_problem(name, n, seed):
+    from paper_2011_04240_amd import scenarios as sc
+    kind = WORKLOADS[name][3]
+    if kind == "swap_sphere":
+        return sc.swap_sphere(n, radius=2.0, seed=seed)
+    if kind == "packed_cube":
+        return sc.packed_cube(n, 0.2, seed=seed)
+    return getattr(sc, kind)(n, seed=seed)
+
+
+def counters_file(name, n, T, B):
+    return os.path.join(PROFILES, "pairwise_%s_n%d_T%d_B%d_counters.txt" % (name, n, T, B))
 
 
 def parse():
@@ -49,6 +71,11 @@ def parse():
                     help="split the problems into this many batches on their own streams (the roofline is "
                          "measured on one batch of all of them)")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--workload", default="box", choices=sorted(WORKLOADS),
+                    help="scene of the timed step (box: the headline; crowded, packed: collisions common; "
+                         "box128: n = 128)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the crowded, packed and n = 128 pairwise workloads")
     ap.add_argument("--T", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--solve", default="dense", choices=["dense", "structured"],
@@ -94,13 +121,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters():
+def traffic_from_counters(path):
     """HBM bytes per pairwise launch from committed rocprofv3 counters, if they were
     taken on the current kernel source (else None)."""
-    if not os.path.exists(COUNTERS_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(COUNTERS_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -131,6 +158,49 @@ def _oracle_iterations(job):
             iters += 1
         dt = time.perf_counter() - t0
     return iters, dt
+
+
+def _oracle_single(job):
+    """The oracle's plan time (K assembly and FP64 inverse) and seconds per iteration of one
+    problem with one BLAS thread: 3 warm-up iterations, then the median of 5 timed ones.
+    Runs in a pool worker."""
+    n, T, seed = job
+    from threadpoolctl import threadpool_limits
+    from oracle import am
+    from paper_2011_04240_amd import scenarios as sc
+    s, g = sc.random_box(n, seed=seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        plan = am.make_plan(n, T, 11, 10.0, 0.3, 0.6, 1.0)
+        plan_s = time.perf_counter() - t0
+        st = am.initial_state(plan, s, g)
+        for _ in range(3):
+            st = am.iterate(plan, st)
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            st = am.iterate(plan, st)
+            times.append(time.perf_counter() - t0)
+    return plan_s, float(np.median(times))
+
+
+def host_description():
+    """CPU model, online cores and the BLAS NumPy was built against."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        blas = "%s %s" % (blas.get("name"), blas.get("version"))
+    except Exception:
+        blas = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "numpy": np.__version__, "blas": blas}
 
 
 def host_cores():
@@ -174,11 +244,16 @@ def cpu_baseline(n, T, seconds, pool=None):
                 "sample": "one n=%d T=%d random-box problem, %d FP64 iterations in %.1f s, BLAS 1 thread"
                           % (n, T, iters, dt)}
     cores = pool.cores
+    plan_s, s_iter = pool.apply(_oracle_single, ((n, T, 0),))
     per = max(2.0, 2.0 * seconds / cores)
     res = pool.map(_oracle_iterations, [(n, T, per, q) for q in range(cores)], chunksize=1)
     rates = [npairs * T * it / dt for it, dt in res]
     return {"value": float(sum(rates)), "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "per_core": float(np.mean(rates)),
+            "per_core": float(np.mean(rates)), "host": host_description(),
+            "single_thread": {"s_per_iteration": s_iter, "updates_per_s": npairs * T / s_iter,
+                              "plan_s": plan_s,
+                              "method": "one n=%d T=%d random-box problem (seed 0), one BLAS thread, "
+                                        "3 warm-up iterations then the median of 5" % (n, T)},
             "sample": "%d processes at once, each one n=%d T=%d random-box problem (seeds 0..%d) iterated in FP64 "
                       "for %.1f s (%d-%d iterations each), BLAS 1 thread per process"
                       % (cores, n, T, cores - 1, per, min(r[0] for r in res), max(r[0] for r in res))}
@@ -551,50 +626,114 @@ def main():
             pool.join()
 
 
-def run_main(args, pool):
+def branch_census(batch, problems, n):
+    """One more iteration of `problems` of the batch, observed through the state hooks: the
+    share of pair-instants that take the pairwise stage's far-pair shortcut (every axis of
+    the multiplier +0 before the step and s^2 > 1.0001 at the step's positions, the test
+    the kernel makes, here in FP64 from the FP32 positions), and the share of multiplier elements whose bits the step changed
+    (the only ones it writes back)."""
+    iu, ju = np.triu_indices(n, 1)
+    before = [batch.get_state(q)["lam"] for q in problems]
+    batch.step(1, use_graph=False)
+    batch.sync()
+    short = changed = total = 0
+    for q, lam0 in zip(problems, before):
+        st = batch.get_state(q, X=True)
+        X = st["X"].astype(np.float64)                # [n][3][T]: the positions of this step
+        d = X[iu] - X[ju]
+        s2 = (d[:, 0] ** 2 + d[:, 1] ** 2) / 0.3 ** 2 + d[:, 2] ** 2 / 0.6 ** 2   # [pair][T]
+        zero = np.all(lam0.view(np.uint32) == 0, axis=-1)
+        short += int(np.count_nonzero(zero & (s2 > 1.0001)))
+        changed += int(np.count_nonzero(lam0.view(np.uint32) != st["lam"].view(np.uint32)))
+        total += zero.size
+    return {"shortcut_frac": short / total, "general_frac": 1.0 - short / total,
+            "written_frac": changed / (3 * total), "sampled_problems": len(problems)}
+
+
+def time_workload(name, T, steps, warmup, precision, solve, autotune=True, warm_iters=None):
+    """Iterations of B problems of one workload in one batch (eager launches, HIP events
+    around every kernel on the batch's stream): seconds per step, the pairwise kernel's
+    average launch, the branch census after the timed steps and the roofline of the
+    pairwise kernel on the method's 24 bytes per pair-instant."""
     import torch
     from paper_2011_04240_amd import mato
-    from paper_2011_04240_amd import scenarios as sc
-
-    n, T, B = args.n, args.T, args.batch
+    desc, n, B, _ = WORKLOADS[name]
     npairs = n * (n - 1) // 2
-    torch.cuda.set_device(0)
-    starts, goals = zip(*[sc.random_box(n, seed=q) for q in range(B)])
+    starts, goals = zip(*[workload_problem(name, n, q) for q in range(B)])
     t0 = time.perf_counter()
-    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, args.precision, solve=args.solve)
+    plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, precision, solve=solve)
     plan_s = time.perf_counter() - t0
     batch = mato.Batch([plan] * B, starts, goals)
-    tiles = batch.autotune() if not args.no_autotune else batch.get_tiles()
-    batch.step(args.warmup, use_graph=False)
+    tiles = batch.autotune() if autotune else batch.get_tiles()
+    batch.step(warmup if warm_iters is None else warm_iters, use_graph=False)
     batch.sync()
     batch.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch.step(args.steps, use_graph=False)
+    batch.step(steps, use_graph=False)
     batch.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms, pw_ms, launches = batch.last_times()
-    updates = npairs * T * B * args.steps
-    value = updates / wall
-    pw_avg_s = pw_ms / max(launches, 1) / 1e3
-    alg_bytes = BYTES_PER_UPDATE * npairs * T * B
-    achieved = alg_bytes / pw_avg_s / 1e9
-    method_bytes = METHOD_BYTES_PER_UPDATE * npairs * T * B
-    traffic = traffic_from_counters() if (n, T, B) == (64, 100, 1024) else None
     batch.timing(False)
-    stream_rd = stream_ceiling(alg_bytes, "read")
-    stream = stream_ceiling(alg_bytes)
-    stream_upd = stream_ceiling(alg_bytes, "update")
+    pw_avg_s = pw_ms / max(launches, 1) / 1e3
+    units = npairs * T * B
     r_max, _, _ = batch.residuals(0)
+    census = branch_census(batch, list(range(min(8, B))), n)
     batch.close()
-    single = {"ms_per_step": wall / args.steps * 1e3, "updates_per_s": value}
+    plan.close()
+    achieved = BYTES_PER_UPDATE * units / pw_avg_s / 1e9
+    traffic = traffic_from_counters(counters_file(name, n, T, B))
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
+            "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * units,
+            "bytes_per_unit": BYTES_PER_UPDATE, "units_per_launch": units,
+            "shortcut_frac": census["shortcut_frac"], "written_frac": census["written_frac"]}
+    if traffic is not None:
+        roof["traffic_GBps"] = traffic / pw_avg_s / 1e9
+        roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
+    return {"workload": desc, "name": name, "n": n, "T": T, "problems": B, "precision": precision, "solve": solve,
+            "ms_per_step": wall / steps * 1e3, "updates_per_s": units * steps / wall,
+            "device_ms_per_step": total_ms / steps, "plan_s": plan_s,
+            "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]}, "census": census, "roofline": roof,
+            "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None}
+
+
+def run_main(args, pool):
+    import torch
+    from paper_2011_04240_amd import mato
+
+    n, T, B = args.n, args.T, args.batch
+    npairs = n * (n - 1) // 2
+    torch.cuda.set_device(0)
+    name = args.workload
+    if (WORKLOADS[name][1], WORKLOADS[name][2]) != (n, B):
+        WORKLOADS[name] = (WORKLOADS[name][0], n, B, WORKLOADS[name][3])
+    head = time_workload(name, T, args.steps, args.warmup, args.precision, args.solve,
+                         autotune=not args.no_autotune)
+    roof = head["roofline"]
+    units = npairs * T * B
+    read_bytes = READ_BYTES_PER_UPDATE * units
+    stream_rd = stream_ceiling(read_bytes, "read")
+    stream = stream_ceiling(read_bytes)
+    stream_upd = stream_ceiling(read_bytes, "update")
+    roof.update({"stream_read": stream_rd, "stream_copy": stream, "stream_update": stream_upd,
+                 "read_bytes_per_launch": read_bytes,
+                 "read_GBps": read_bytes / (roof["avg_launch_ms"] * 1e-3) / 1e9})
+    roof["read_frac_of_stream_read"] = roof["read_GBps"] / stream_rd["GBps"]
+    if roof["traffic"] is not None:
+        roof["traffic_frac_of_stream_read"] = roof["traffic_GBps"] / stream_rd["GBps"]
+    single = {"ms_per_step": head["ms_per_step"], "updates_per_s": head["updates_per_s"]}
+    value, ms_per_step = head["updates_per_s"], head["ms_per_step"]
     if args.streams > 1:
-        sec = multi_stream_step(plan, starts, goals, args.streams, tiles, args.steps, args.warmup)
-        value = npairs * T * B / sec
+        starts, goals = zip(*[workload_problem(name, n, q) for q in range(B)])
+        plan = mato.Plan(n, T, 11, 10.0, 0.3, 0.6, 1.0, args.precision, solve=args.solve)
+        sec = multi_stream_step(plan, starts, goals, args.streams, (head["tiles"]["items_per_wg"],
+                                head["tiles"]["threads"]), args.steps, args.warmup)
+        plan.close()
+        value = units / sec
         ms_per_step = sec * 1e3
-    else:
-        ms_per_step = wall / args.steps * 1e3
     out = {
         "metric": "pair-timestep updates/s at n=64,T=100",
         "value": value,
@@ -608,24 +747,24 @@ def run_main(args, pool):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "random-box problems, n=%d agents, T=%d instants, %d problems per launch" % (n, T, B),
+        "config": {"workload": "%s, n=%d agents, T=%d instants, %d problems per launch" % (head["workload"], n, T, B),
                    "n": n, "T": T, "problems": B, "precision": args.precision, "solve": args.solve,
-                   "streams": args.streams,
-                   "tiles": {"items_per_wg": tiles[0], "threads": tiles[1]},
-                   "device_ms_per_step": total_ms / args.steps, "plan_s": plan_s},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "stream_read": stream_rd, "frac_of_stream_read": achieved / stream_rd["GBps"],
-                     "method_bytes_per_launch": method_bytes,
-                     "method_GBps": method_bytes / pw_avg_s / 1e9,
-                     "stream_copy": stream, "stream_update": stream_upd},
-        "final_r_max_problem0": float(r_max[-1]) if len(r_max) else None,
+                   "streams": args.streams, "tiles": head["tiles"],
+                   "device_ms_per_step": head["device_ms_per_step"], "plan_s": head["plan_s"]},
+        "roofline": roof,
+        "census": head["census"],
+        "final_r_max_problem0": head["final_r_max_problem0"],
         "single_stream": single,
     }
     if args.solve == "dense":
+        starts, goals = zip(*[workload_problem(name, n, q) for q in range(B)])
         out["structured_step"] = structured_step(n, T, B, starts, goals, args)
+    if not args.no_workloads:
+        # the pairwise stage where collisions are common (its general branch) and at the
+        # largest agent count of the serving configuration; warmed 30 iterations
+        out["workloads"] = [time_workload(w, T, args.steps, 30, args.precision, args.solve,
+                                          autotune=not args.no_autotune)
+                            for w in ("crowded", "packed", "box128") if w != name]
     if not args.no_mixed:
         out["batch_scaling"] = batch_scaling(n, T)
     if not args.no_serve:

@@ -72,6 +72,15 @@ def random_density_box(n, min_sep=1.0, seed=0):
     return random_box(n, box=density_box(n), min_sep=min_sep, seed=seed)
 
 
+def packed_cube(n, side=0.2, seed=0):
+    """Starts and goals drawn independently and uniformly in a cube of the given side,
+    no separation: with side 0.2 m every pair of agents of semi-axes (0.3, 0.6) m
+    overlaps at both ends of the horizon (a stress case in which every pair carries a
+    multiplier, not a feasible plan)."""
+    rng = _rng(seed)
+    return rng.uniform(0.0, side, size=(n, 3)), rng.uniform(0.0, side, size=(n, 3))
+
+
 def agent_counts(count, choices, seed=0):
     """Seeded uniform draw of agent counts from `choices`."""
     rng = _rng(seed)
