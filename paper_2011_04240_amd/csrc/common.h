@@ -136,7 +136,8 @@ struct GemmTile {               // one 64-row output tile (64 or 48 columns) of 
 
 struct GemmGroup {              // problems sharing one plan: C[:, col] = c_eq + K11^{-1} B[:, col]
     const void* Ahi;            // [Mp][ldk] K11^{-1} (fp32 / bf16 hi / fp64), zero padded
-    const void* Alo;            // bf16 lo (BF16 split only)
+    const void* Amid;           // bf16 middle term (BF16 split only)
+    const void* Alo;            // bf16 low term (BF16 split only)
     int M, K, ldk;              // 11n, 11n, padded row stride of A (multiple of 32)
     int ncols;                  // 3 x members
     int first_col;              // offset into the column table
@@ -172,8 +173,8 @@ struct mato_plan_s {
     std::vector<double> Ks0, Ksn;  // structured solve: inverses of K_0 and K_{rho n}, (nv+6)^2 FP64
     double* dS = nullptr;        // structured solve: [nv][nv] M1, [nv][nv] M2, [nv][6] E0, [nv][6] En
     unsigned* dPairs = nullptr;  // [n(n-1)/2 + n n_obs] row p -> i | j << 16 in the row order of A_fc
-    void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 hi or fp64
-    void* dAlo = nullptr;        // bf16 lo part
+    void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 high term or fp64
+    void* dAlo = nullptr;        // bf16 middle and low terms, one [Mp][ldk] plane each
     int ldk = 0;                 // padded row stride of the GEMM operand
     size_t bytes = 0;            // device bytes held
 };

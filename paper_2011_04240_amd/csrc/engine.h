@@ -437,7 +437,9 @@ struct Engine {
             const auto& mem = members[pl];
             GemmGroup G;
             G.Ahi = pl->dAhi;
-            G.Alo = pl->dAlo;
+            G.Amid = pl->dAlo;
+            G.Alo = pl->dAlo ? (const void*)((const unsigned short*)pl->dAlo +
+                                             (size_t)round_up(pl->n * pl->nv, 64) * pl->ldk) : nullptr;
             G.M = pl->n * pl->nv;
             G.K = pl->n * pl->nv;
             G.ldk = pl->ldk;

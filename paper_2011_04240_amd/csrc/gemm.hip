@@ -9,8 +9,8 @@
 // Tiles are 64 rows x 64 right-hand sides; in each group of 4 wavefronts a
 // wavefront owns a 32 x 32 quadrant computed as 2 x 2 blocks of 16 x 16 MFMA outputs.
 //   gemm_f32   v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation.
-//   gemm_bf16  v_mfma_f32_16x16x32_bf16 over two-term BF16 splits of both
-//              operands (hi*hi + hi*lo + lo*hi), FP32 accumulation.
+//   gemm_bf16  v_mfma_f32_16x16x32_bf16 over three-term BF16 splits of both
+//              operands (the six products down to 2^-16 relative), FP32 accumulation.
 //   gemm_f64   FP64 FMA (the reference-precision path).
 // The MFMA kernels read the FP32 copy of the right-hand sides (the BF16 kernel
 // splits it on the way into LDS); the product is added to the FP64
@@ -302,36 +302,46 @@ __global__ __launch_bounds__(512) void gemm_f32_w48(const GemmTile* __restrict__
     finish_tile_w48(t, G, cols, acc, smem, grp, wq, lane, accumulate);
 }
 
-__device__ inline void split8(const float4& x0, const float4& x1, ushortx8& hi, ushortx8& lo) {
+// An FP32 value as the sum of three bf16 terms, hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid): exact (8 + 8 + 8 significant bits), each difference exact in FP32.
+__device__ inline void split8x3(const float4& x0, const float4& x1, ushortx8& hi, ushortx8& mid, ushortx8& lo) {
     const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const unsigned short h = f2bf_rne(v[e]);
+        const float r1 = v[e] - bf2f(h);
+        const unsigned short m = f2bf_rne(r1);
         hi[e] = h;
-        lo[e] = f2bf_rne(v[e] - bf2f(h));
+        mid[e] = m;
+        lo[e] = f2bf_rne(r1 - bf2f(m));
     }
 }
 
+// Three-term BF16 split of both operands, A = Ah + Am + Al (from the FP64 inverse) and
+// B = Bh + Bm + Bl (exact for the FP32 right-hand side): six v_mfma_f32_16x16x32_bf16
+// per block and step (hh, hm, mh, hl, lh, mm); the dropped terms (ml, lm, ll) are below
+// 2^-23 of |A||B|, so the product carries FP32's precision at BF16 MFMA rates.
 __global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ tiles,
                                                  const GemmGroup* __restrict__ groups,
                                                  const GemmCol* __restrict__ cols, int accumulate) {
     const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
     constexpr int LDH = 40;                                   // [row][k] stride in bf16 elements
-    __shared__ __align__(16) unsigned short smem[2 * 4 * 64 * LDH];
+    constexpr int PL = 64 * LDH;                              // one staged plane
+    __shared__ __align__(16) unsigned short smem[2 * 6 * PL];
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = gt & 63, wq = gt >> 6;
     const int wm = wq >> 1, wn = wq & 1;
     const int lr = gt & 63, kq = (gt >> 6) * 8;
-    unsigned short* Ah = smem + grp * 4 * 64 * LDH;
-    unsigned short* Al = Ah + 64 * LDH;
-    unsigned short* Bh = Al + 64 * LDH;
-    unsigned short* Bl = Bh + 64 * LDH;
+    unsigned short* As = smem + grp * 6 * PL;                 // Ah, Am, Al, Bh, Bm, Bl
+    unsigned short* Bs = As + 3 * PL;
     bool act;
     const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
     if (!__syncthreads_or(act)) return;
-    const unsigned short* ahi = (const unsigned short*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
-    const unsigned short* alo = (const unsigned short*)G.Alo + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const size_t aoff = (size_t)(t.m0 + lr) * G.ldk + kq;
+    const unsigned short* ahi = (const unsigned short*)G.Ahi + aoff;
+    const unsigned short* amd = (const unsigned short*)G.Amid + aoff;
+    const unsigned short* alo = (const unsigned short*)G.Alo + aoff;
     const int nk = G.ldk / 32;
     const int nsteps = (nk + 1) / 2;
     floatx4 acc[2][2];
@@ -339,12 +349,13 @@ __global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ ti
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    ushortx8 vh, vl;
+    ushortx8 vh, vm, vl;
     float4 rb0, rb1;
     auto fetch = [&](int s) {
         const int k0 = (2 * s + grp) * 32;
         if (k0 < G.ldk) {
             vh = *(const ushortx8*)(ahi + k0);
+            vm = *(const ushortx8*)(amd + k0);
             vl = *(const ushortx8*)(alo + k0);
             rb0 = *(const float4*)(brow + k0);
             rb1 = *(const float4*)(brow + k0 + 4);
@@ -353,39 +364,47 @@ __global__ __launch_bounds__(512) void gemm_bf16(const GemmTile* __restrict__ ti
     fetch(0);
     for (int s = 0; s < nsteps; ++s) {
         const bool valid = (2 * s + grp) < nk;
-        ushortx8 bh, bl;
-        if (valid) split8(rb0, rb1, bh, bl);
+        ushortx8 bh, bm, bl;
+        if (valid) split8x3(rb0, rb1, bh, bm, bl);
         __syncthreads();
         if (valid) {
-            *(ushortx8*)&Ah[lr * LDH + kq] = vh;
-            *(ushortx8*)&Al[lr * LDH + kq] = vl;
-            *(ushortx8*)&Bh[lr * LDH + kq] = bh;
-            *(ushortx8*)&Bl[lr * LDH + kq] = bl;
+            *(ushortx8*)&As[lr * LDH + kq] = vh;
+            *(ushortx8*)&As[PL + lr * LDH + kq] = vm;
+            *(ushortx8*)&As[2 * PL + lr * LDH + kq] = vl;
+            *(ushortx8*)&Bs[lr * LDH + kq] = bh;
+            *(ushortx8*)&Bs[PL + lr * LDH + kq] = bm;
+            *(ushortx8*)&Bs[2 * PL + lr * LDH + kq] = bl;
         }
         __syncthreads();
         if (s + 1 < nsteps) fetch(s + 1);
         if (valid) {
             const int kb = 8 * (lane >> 4);
-            bf16x8 a_h[2], a_l[2], b_h[2], b_l[2];
+            bf16x8 a[3][2], b[3][2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int m = wm * 32 + i * 16 + (lane & 15);
-                a_h[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Ah[m * LDH + kb]);
-                a_l[i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Al[m * LDH + kb]);
-            }
+            for (int p = 0; p < 3; ++p) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c = wn * 32 + j * 16 + (lane & 15);
-                b_h[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bh[c * LDH + kb]);
-                b_l[j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bl[c * LDH + kb]);
+                for (int i = 0; i < 2; ++i) {
+                    const int m = wm * 32 + i * 16 + (lane & 15);
+                    a[p][i] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&As[p * PL + m * LDH + kb]);
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int c = wn * 32 + j * 16 + (lane & 15);
+                    b[p][j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)&Bs[p * PL + c * LDH + kb]);
+                }
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_h[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[i], b_l[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[i], b_h[j], acc[i][j], 0, 0, 0);
+                    floatx4 x = acc[i][j];
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], x, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], x, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], x, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], x, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], x, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], x, 0, 0, 0);
+                    acc[i][j] = x;
                 }
         }
     }

@@ -4,7 +4,7 @@
 //
 // The inverse is taken on the device by Gauss-Jordan elimination with partial
 // pivoting on the augmented matrix [K | I]; the c-rows [K11^{-1} | K12^{-1}] are
-// then stored in the arithmetic of the per-iteration product (FP32, a two-term
+// then stored in the arithmetic of the per-iteration product (FP32, a three-term
 // BF16 split, or FP64).
 #include <cmath>
 #include <cstdarg>
@@ -215,7 +215,11 @@ __device__ inline float bf16_bits_to_float(unsigned short h) {
 }
 
 // GEMM operand: the leading M x M block of K^{-1} (row stride N), zero-padded to Mp x ldk.
-// kind 0: fp32; 1: bf16 hi + lo (hi = bf16(x), lo = bf16(fp32(x) - hi)); 2: fp64.
+// kind 0: fp32; 1: three bf16 terms of the FP64 value, hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid) (differences in FP64: 24 significant bits in all); 2: fp64.
+__device__ inline unsigned short bf16_bits_rne_f64(double x) {
+    return bf16_bits_rne((float)x);   // a double within FP32 range rounds to bf16 through fp32
+}
 __global__ void extract_crows(const double* __restrict__ inv, int N, int M, int Mp, int ldk,
                               int kind, void* __restrict__ hi, void* __restrict__ lo) {
     const size_t total = (size_t)Mp * ldk;
@@ -226,10 +230,13 @@ __global__ void extract_crows(const double* __restrict__ inv, int N, int M, int 
         if (kind == 0) {
             ((float*)hi)[e] = (float)v;
         } else if (kind == 1) {
-            const float x = (float)v;
-            const unsigned short h = bf16_bits_rne(x);
+            const unsigned short h = bf16_bits_rne_f64(v);
+            const double r1 = v - (double)bf16_bits_to_float(h);
+            const unsigned short m = bf16_bits_rne_f64(r1);
+            const double r2 = r1 - (double)bf16_bits_to_float(m);
             ((unsigned short*)hi)[e] = h;
-            ((unsigned short*)lo)[e] = bf16_bits_rne(x - bf16_bits_to_float(h));
+            ((unsigned short*)lo)[e] = m;
+            ((unsigned short*)lo)[total + e] = bf16_bits_rne_f64(r2);
         } else {
             ((double*)hi)[e] = v;
         }
@@ -434,8 +441,8 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         MATO_TRY(dalloc((char**)&p->dAhi, esz * elems));
         p->bytes += esz * elems;
         if (kind == 1) {
-            MATO_TRY(dalloc((char**)&p->dAlo, esz * elems));
-            p->bytes += esz * elems;
+            MATO_TRY(dalloc((char**)&p->dAlo, 2 * esz * elems));
+            p->bytes += 2 * esz * elems;
         }
         extract_crows<<<grid_for(elems, 256), 256, 0, st>>>(p->dKinv, N, M, Mp, ldk, kind, p->dAhi, p->dAlo);
     }

@@ -126,8 +126,6 @@ def test_batching_config_against_oracle():
             assert v < 1e-3, (q, n, k, v, err)
 
 
-@pytest.mark.skip(reason="two-term BF16 split: a 12-agent request ends 3.9e-3 off the oracle in max ||f_c|| "
-                         "after 184 iterations (c 9.3e-5); the three-term split replaces it")
 def test_serving_config_bf16_dense_against_oracle():
     """Served requests in the configuration's arithmetic (dense product in the BF16 split,
     FP64 corrections, FP32 state), fixed rho = 1, tolerance 1e-3 m, cap 2000, T = 100."""
