@@ -342,7 +342,9 @@ mato_status mato_server_run_trace(mato_server s, int32_t count, const double* ar
 
 /* ------------------------------------------------------ single problem ---
  * Convenience wrappers: a solve is a batch of one (same handle type).
- * mato_solve_run creates the solve and runs it as mato_batch_run; if the run itself
+ * mato_solve_run runs Algorithm 1 on one problem: the initialisation, then passes of
+ * its while-loop until `iters` passes or max ||f_c|| < tol (tested every check_every
+ * passes), as mato_batch_run.  It creates the solve; if the run itself
  * fails (NONFINITE, HIP) *out still holds the solve, for inspection, and the caller
  * destroys it; if creation fails *out is NULL. */
 typedef struct mato_batch_s* mato_solve;
@@ -358,6 +360,33 @@ mato_status mato_step(mato_solve s, int32_t k_steps);
 mato_status mato_get_state(mato_solve s, void* c, void* lambda, void* proj, void* d, void* X);
 mato_status mato_set_state(mato_solve s, const void* c, const void* lambda, const void* proj);
 void        mato_solve_destroy(mato_solve s);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same whole solve as
+ * mato_solve_run + mato_solve_sync + mato_solve_coeffs + mato_residuals +
+ * mato_batch_status + mato_solve_destroy, with every device buffer it needs carved
+ * from a fixed array of MATO_NOALLOC_SCRATCH_BYTES per device that the library holds
+ * until the process ends.  It calls no hipMalloc / hipFree and creates no graph; it is
+ * synchronous on the plan's stream and returns when the results are written.
+ *   plan         a plan without static obstacles (created beforehand: plan creation
+ *                allocates); its precision and solve kind select the arithmetic
+ *   starts/goals [n][3] FP64, host or device
+ *   c            out [n][3][n_coef] FP64, host or device
+ *   r_max, r_rms, cost  out, per iteration as mato_residuals (each may be NULL),
+ *                at most `cap` entries, *n_written set (may be NULL)
+ *   iters_done, converged  out, as mato_batch_status (each may be NULL)
+ * Errors: INVALID_ARG (null plan/starts/goals/c, iters < 0, check_every < 1, a plan
+ * with obstacles), UNSUPPORTED (the problem's state does not fit the fixed array: about
+ * 12 n(n-1)/2 T bytes in FP32, twice that in FP64, plus under 200 KB), NONFINITE, HIP;
+ * NOT_CONVERGED (warning) when tol > 0 is not met.  Calls on one device share its array:
+ * the library serialises them with a lock per device (host threads of one process);
+ * every call clears what it reads before use, and its results are copied out before
+ * it returns. */
+#define MATO_NOALLOC_SCRATCH_BYTES (32u << 20)
+mato_status mato_solve_noalloc(mato_plan plan, const double* starts, const double* goals,
+                               int32_t iters, double tol, int32_t check_every, double* c,
+                               double* r_max, double* r_rms, double* cost, int32_t cap,
+                               int32_t* n_written, int32_t* iters_done, int32_t* converged);
 
 /* --------------------------------------------------------------- streams ---
  * A HIP stream of the library's own runtime (non-blocking, default priority), for

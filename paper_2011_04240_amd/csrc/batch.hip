@@ -1,6 +1,8 @@
 // C ABI of batches and single solves (include/mato.h) on top of the engine
 // (engine.h): a fixed set of independent problems placed in one device arena and
 // advanced together, one pass of the while-loop of Algorithm 1 per iteration.
+#include <mutex>
+
 #include "engine.h"
 
 namespace mato {
@@ -11,11 +13,15 @@ template <typename S>
 using BatchImpl = Engine<S>;
 
 // ----------------------------------------------------------- creation ---
+// ext: when not null, every device buffer of the batch is carved from this region of
+// ext_cap bytes (no device allocation, no graphs, no pinned staging).
 template <typename S>
 static mato_status batch_create(int count, const mato_plan* plans, const double* starts,
                                 const double* goals, const double* obstacles, hipStream_t st,
-                                BatchImpl<S>** out) {
+                                BatchImpl<S>** out, char* ext = nullptr, size_t ext_cap = 0) {
     auto* B = new BatchImpl<S>();
+    B->ext = ext;
+    B->ext_cap = ext_cap;
     B->precision = plans[0]->precision;
     B->solve = plans[0]->solve;
     B->refine = (B->precision == MATO_FP32) ? 1 : (B->precision == MATO_BF16_REFINED ? 2 : 0);
@@ -47,7 +53,10 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
     mato_status s;
     if ((s = B->init_capacity(count)) != MATO_OK) return fail(s);
     B->arena_bytes = std::max<size_t>(total, 256);
-    if (hipMalloc(&B->arena, B->arena_bytes) != hipSuccess) {
+    if (ext) {
+        size_t cap = 0;
+        if ((s = B->dev_buf(&B->arena, &cap, B->arena_bytes)) != MATO_OK) return fail(s);
+    } else if (hipMalloc(&B->arena, B->arena_bytes) != hipSuccess) {
         (void)hipGetLastError();
         set_error("device allocation of %zu bytes failed", B->arena_bytes);
         return fail(MATO_ERR_OUT_OF_MEMORY);
@@ -474,4 +483,76 @@ extern "C" mato_status mato_stream_destroy(void* stream) {
     if (!stream) { set_error("null stream"); return MATO_ERR_INVALID_ARG; }
     MATO_HIP(hipStreamDestroy((hipStream_t)stream));
     return MATO_OK;
+}
+
+// ------------------------------------------------- solve without allocation ---
+// A fixed device array for callers that cannot allocate: every device buffer of
+// mato_solve_noalloc (problem state, descriptors, work lists, control words) is carved
+// from it.  Each device holds its own copy for the life of the process; host code uses
+// only the address hipGetSymbolAddress returns for the current device, never the name.
+namespace mato {
+constexpr size_t kScratchBytes = (size_t)MATO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu[kMaxDevices];     // one call at a time per device
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of the array (looked up once per device, with
+// that device current, under its lock).
+static mato_status scratch_base(int dev, char** out) {
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+            return MATO_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = (char*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MATO_OK;
+}
+}  // namespace mato
+
+extern "C" mato_status mato_solve_noalloc(mato_plan plan, const double* starts, const double* goals,
+                                          int32_t iters, double tol, int32_t check_every, double* c,
+                                          double* r_max, double* r_rms, double* cost, int32_t cap,
+                                          int32_t* n_written, int32_t* iters_done, int32_t* converged) {
+    if (!plan || !starts || !goals || !c) { set_error("null argument"); return MATO_ERR_INVALID_ARG; }
+    if (iters < 0 || check_every < 1) { set_error("iters must be >= 0 and check_every >= 1"); return MATO_ERR_INVALID_ARG; }
+    int dev = 0;
+    MATO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) { set_error("device %d beyond %d", dev, kMaxDevices); return MATO_ERR_UNSUPPORTED; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    char* base = nullptr;
+    MATO_TRY(scratch_base(dev, &base));
+    mato_batch_s b;
+    b.precision = plan->precision;
+    mato_status s;
+    if (b.precision == MATO_FP64) {
+        BatchImpl<double>* B = nullptr;
+        s = batch_create<double>(1, &plan, starts, goals, nullptr, plan->stream, &B, base, kScratchBytes);
+        b.impl = B;
+    } else {
+        BatchImpl<float>* B = nullptr;
+        s = batch_create<float>(1, &plan, starts, goals, nullptr, plan->stream, &B, base, kScratchBytes);
+        b.impl = B;
+    }
+    if (s == MATO_OK) {
+        const mato_status r = mato_batch_run(&b, iters, tol, check_every);
+        s = (r < 0) ? r : MATO_OK;
+        if (s == MATO_OK) s = mato_batch_coeffs(&b, 0, c);
+        if (s == MATO_OK) s = mato_batch_residuals(&b, 0, r_max, r_rms, cost, cap, n_written);
+        if (s == MATO_OK) s = mato_batch_status(&b, 0, iters_done, converged);
+        if (s == MATO_OK) s = r;                       // keep the NOT_CONVERGED warning
+    }
+    if (b.impl) {
+        if (b.precision == MATO_FP64)
+            delete static_cast<BatchImpl<double>*>(b.impl);
+        else
+            delete static_cast<BatchImpl<float>*>(b.impl);
+    }
+    return s;
 }

@@ -165,7 +165,39 @@ struct Engine {
     int pw_used = 0;
     bool last_timed = false;
 
+    // Device memory carved from a caller-provided region instead of hipMalloc (entry points
+    // that must not allocate): 256-byte steps, never freed by the engine; uploads then copy
+    // straight from the caller's host memory and iterations are launched eagerly (no graphs).
+    char* ext = nullptr;
+    size_t ext_cap = 0, ext_used = 0;
+
+    template <typename T>
+    mato_status dev_buf(T** p, size_t* cap, size_t count) {
+        if (!ext) return ensure_device(p, cap, count);
+        if (*p && *cap >= count) return MATO_OK;
+        const size_t n = std::max<size_t>(count, 1);
+        const size_t bytes = (sizeof(T) * n + 255) & ~(size_t)255;
+        if (ext_used + bytes > ext_cap) {
+            set_error("the problem needs more than the %zu bytes of the fixed device scratch", ext_cap);
+            return MATO_ERR_UNSUPPORTED;
+        }
+        *p = reinterpret_cast<T*>(ext + ext_used);
+        ext_used += bytes;
+        *cap = n;
+        return MATO_OK;
+    }
+
     ~Engine() {
+        if (ext) {                        // carved from the caller's region: nothing to free
+            arena = nullptr;
+            dctrl = nullptr;
+            ddesc = nullptr;
+            dk0c = dkinv = nullptr;
+            ditems = dscratch = nullptr;
+            dgroups = nullptr;
+            dtiles = nullptr;
+            dcolsq = dcolsr = nullptr;
+        }
         if (ring) (void)hipHostFree(ring);
         if (g1) (void)hipGraphExecDestroy(g1);
         if (gC) (void)hipGraphExecDestroy(gC);
@@ -194,6 +226,11 @@ struct Engine {
     // Stream-ordered copy of `bytes` host bytes to `dst`; `src` may be reused on return.
     mato_status upload(void* dst, const void* src, size_t bytes) {
         if (bytes == 0) return MATO_OK;
+        if (ext) {                                       // no staging ring: copy and wait
+            MATO_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+            MATO_HIP(hipStreamSynchronize(stream));
+            return MATO_OK;
+        }
         if (!ring && hipHostMalloc((void**)&ring, kRingBytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             ring = nullptr;
@@ -283,15 +320,19 @@ struct Engine {
         hdesc.assign(cap, ProblemDesc<S>());
         hk0c.assign(cap, nullptr);
         hkinv.assign(cap, nullptr);
-        MATO_HIP(hipMalloc(&dctrl, sizeof(int) * kCtrl * cap));
-        MATO_HIP(hipMemset(dctrl, 0, sizeof(int) * kCtrl * cap));
-        MATO_HIP(hipMalloc(&ddesc, sizeof(ProblemDesc<S>) * cap));
-        MATO_HIP(hipMalloc(&dk0c, sizeof(double*) * cap));
-        MATO_HIP(hipMalloc(&dkinv, sizeof(double*) * cap));
-        MATO_HIP(hipMemset(dk0c, 0, sizeof(double*) * cap));
-        MATO_HIP(hipMemset(dkinv, 0, sizeof(double*) * cap));
-        if (!ev0) MATO_HIP(hipEventCreate(&ev0));
-        if (!ev1) MATO_HIP(hipEventCreate(&ev1));
+        size_t c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+        MATO_TRY(dev_buf(&dctrl, &c1, (size_t)kCtrl * cap));
+        MATO_TRY(dev_buf(&ddesc, &c2, (size_t)cap));
+        MATO_TRY(dev_buf(&dk0c, &c3, (size_t)cap));
+        MATO_TRY(dev_buf(&dkinv, &c4, (size_t)cap));
+        MATO_HIP(hipMemsetAsync(dctrl, 0, sizeof(int) * kCtrl * cap, stream));
+        MATO_HIP(hipMemsetAsync(dk0c, 0, sizeof(double*) * cap, stream));
+        MATO_HIP(hipMemsetAsync(dkinv, 0, sizeof(double*) * cap, stream));
+        MATO_HIP(hipStreamSynchronize(stream));
+        if (!ext) {                                      // HIP events only for timing
+            if (!ev0) MATO_HIP(hipEventCreate(&ev0));
+            if (!ev1) MATO_HIP(hipEventCreate(&ev1));
+        }
         return MATO_OK;
     }
 
@@ -402,7 +443,7 @@ struct Engine {
         for (int q = 0; q < count(); ++q)
             if (probs[q].active) slot_items(q, hitems, &maxlds, q);
         lds = maxlds;
-        MATO_TRY(ensure_device(&ditems, &ditems_cap, hitems.size()));
+        MATO_TRY(dev_buf(&ditems, &ditems_cap, hitems.size()));
         if (!hitems.empty())
             MATO_TRY(upload(ditems, hitems.data(), sizeof(WorkItem) * hitems.size()));
         if (lds > 0 && set_pairwise_lds_limit<S>(lds) != hipSuccess) {
@@ -464,10 +505,10 @@ struct Engine {
             for (int c0 = 0; c0 < G.ncols; c0 += gemm_width)
                 for (int m0 = 0; m0 < Mp; m0 += 64) htiles.push_back(GemmTile{(int)g, m0, c0, 0});
         }
-        MATO_TRY(ensure_device(&dgroups, &cap_groups, hgroups.size()));
-        MATO_TRY(ensure_device(&dtiles, &cap_tiles, htiles.size()));
-        MATO_TRY(ensure_device(&dcolsq, &cap_colsq, colq.size()));
-        MATO_TRY(ensure_device(&dcolsr, &cap_colsr, colr.size()));
+        MATO_TRY(dev_buf(&dgroups, &cap_groups, hgroups.size()));
+        MATO_TRY(dev_buf(&dtiles, &cap_tiles, htiles.size()));
+        MATO_TRY(dev_buf(&dcolsq, &cap_colsq, colq.size()));
+        MATO_TRY(dev_buf(&dcolsr, &cap_colsr, colr.size()));
         if (!hgroups.empty()) {
             MATO_TRY(upload(dgroups, hgroups.data(), sizeof(GemmGroup) * hgroups.size()));
             MATO_TRY(upload(dtiles, htiles.data(), sizeof(GemmTile) * htiles.size()));
@@ -625,7 +666,7 @@ struct Engine {
         if (dscratch_cap < items.size()) {
             // the list of an earlier slot's initialisation may still be in use: let it finish first
             MATO_HIP(hipStreamSynchronize(stream));
-            MATO_TRY(ensure_device(&dscratch, &dscratch_cap, std::max<size_t>(items.size(), (size_t)probs[q].T)));
+            MATO_TRY(dev_buf(&dscratch, &dscratch_cap, std::max<size_t>(items.size(), (size_t)probs[q].T)));
         }
         MATO_TRY(upload(dscratch, items.data(), sizeof(WorkItem) * items.size()));
         const int nv = probs[q].nv == 11 ? 11 : 0;
@@ -713,6 +754,7 @@ struct Engine {
     }
 
     mato_status run_segment(int k, bool use_graph, bool per_kernel_events) {
+        if (ext) use_graph = false;       // instantiating a graph may allocate
         if (lists_dirty) MATO_TRY(rebuild_lists());
         if (active_count() == 0 || k <= 0) return MATO_OK;
         if (use_graph) {

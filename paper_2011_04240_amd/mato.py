@@ -113,6 +113,7 @@ SIGNATURES = {
     "mato_step": (_i32, [_vp, _i32]),
     "mato_get_state": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mato_set_state": (_i32, [_vp, _vp, _vp, _vp]),
+    "mato_solve_noalloc": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _i32, _pi32, _pi32, _pi32]),
     "mato_stream_copy": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
     "mato_stream_update": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
     "mato_stream_read": (_i32, [ctypes.c_int64, _i32, _i32, _vp, _pf64]),
@@ -431,6 +432,15 @@ def mato_set_state(solve, c, lam, proj):
 
 def mato_solve_destroy(solve):
     lib().mato_solve_destroy(solve)
+
+
+def mato_solve_noalloc(plan, starts, goals, iters, tol, check_every, c, r_max, r_rms, cost, cap):
+    """Returns (status, entries written, iterations done, converged)."""
+    nw, it, conv = _i32(), _i32(), _i32()
+    status = _check(lib().mato_solve_noalloc(plan, _ptr(starts), _ptr(goals), iters, tol, check_every, _ptr(c),
+                                             _ptr(r_max), _ptr(r_rms), _ptr(cost), cap, ctypes.byref(nw),
+                                             ctypes.byref(it), ctypes.byref(conv)))
+    return status, nw.value, it.value, conv.value
 
 
 def mato_stream_copy(nbytes, grid=1024, iters=10, stream=None):
