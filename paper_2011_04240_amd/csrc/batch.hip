@@ -230,13 +230,15 @@ static mato_status get_state_impl(BatchImpl<S>* B, int q, void* c, void* lambda,
     MATO_HIP(hipStreamSynchronize(B->stream));
     (void)c;
     const size_t npt = (size_t)P.np * P.T;
+    std::vector<int> canon(P.np);                   // internal row -> canonical row
+    for (int r = 0; r < P.np; ++r) canon[r] = canonical_row(P.plan->pairs[r], P.n, P.n_obs);
     auto pairwise_out = [&](const S* dsrc, void* dst) -> mato_status {
         std::vector<S> h(npt * 3), o(npt * 3);
         MATO_HIP(hipMemcpy(h.data(), dsrc, sizeof(S) * h.size(), hipMemcpyDeviceToHost));
         for (int t = 0; t < P.T; ++t)
             for (int a = 0; a < 3; ++a)
-                for (int p = 0; p < P.np; ++p)
-                    o[((size_t)p * P.T + t) * 3 + a] = h[((size_t)t * 3 + a) * P.np + p];
+                for (int r = 0; r < P.np; ++r)
+                    o[((size_t)canon[r] * P.T + t) * 3 + a] = h[((size_t)t * 3 + a) * P.np + r];
         return copy_out(dst, o.data(), sizeof(S) * o.size());
     };
     if (lambda) MATO_TRY(pairwise_out((const S*)(P.base + P.o_lam), lambda));
@@ -247,7 +249,7 @@ static mato_status get_state_impl(BatchImpl<S>* B, int q, void* c, void* lambda,
         std::vector<S> h(npt), o(npt);
         MATO_HIP(hipMemcpy(h.data(), D.dbg_d, sizeof(S) * npt, hipMemcpyDeviceToHost));
         for (int t = 0; t < P.T; ++t)
-            for (int p = 0; p < P.np; ++p) o[(size_t)p * P.T + t] = h[(size_t)t * P.np + p];
+            for (int r = 0; r < P.np; ++r) o[(size_t)canon[r] * P.T + t] = h[(size_t)t * P.np + r];
         MATO_TRY(copy_out(d, o.data(), sizeof(S) * npt));
     }
     if (X) {
@@ -276,13 +278,16 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     const size_t npt = (size_t)P.np * P.T;
     MATO_HIP(hipStreamSynchronize(B->stream));
     std::vector<S> in(npt * 3), lam_i(npt * 3), proj_i(npt * 3);
+    std::vector<int> canon(P.np);                   // internal row -> canonical row
+    for (int r = 0; r < P.np; ++r) canon[r] = canonical_row(P.plan->pairs[r], P.n, P.n_obs);
     auto to_internal = [&](const void* src, std::vector<S>& dst) -> mato_status {
         MATO_HIP(hipMemcpy(in.data(), src, sizeof(S) * in.size(), hipMemcpyDefault));
         for (size_t e = 0; e < in.size(); ++e)
             if (!std::isfinite((double)in[e])) { set_error("non-finite state"); return MATO_ERR_NONFINITE; }
-        for (int p = 0; p < P.np; ++p)
+        for (int r = 0; r < P.np; ++r)
             for (int t = 0; t < P.T; ++t)
-                for (int a = 0; a < 3; ++a) dst[((size_t)t * 3 + a) * P.np + p] = in[((size_t)p * P.T + t) * 3 + a];
+                for (int a = 0; a < 3; ++a)
+                    dst[((size_t)t * 3 + a) * P.np + r] = in[((size_t)canon[r] * P.T + t) * 3 + a];
         return MATO_OK;
     };
     MATO_TRY(to_internal(lambda, lam_i));

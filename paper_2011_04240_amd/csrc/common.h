@@ -78,6 +78,14 @@ struct DevBuf {
 // Pair p = (i, j), i < j, in the row order of A_fc: p(i, j) = i n - i(i+1)/2 + j - i - 1.
 __host__ __device__ inline int row_offset(int i, int n) { return i * n - i * (i + 1) / 2; }
 
+// Canonical collision row (agent pairs in the row order of A_fc, then agent-obstacle rows
+// agent-major) of a pair-table entry i | j << 16 (partner j >= n: obstacle j - n).
+__host__ __device__ inline int canonical_row(unsigned code, int n, int n_obs) {
+    const int i = (int)(code & 0xffffu), j = (int)(code >> 16);
+    if (j < n) return row_offset(i, n) + j - i - 1;
+    return n * (n - 1) / 2 + i * n_obs + (j - n);
+}
+
 // -------------------------------------------------------- device descriptors ---
 // One problem as the kernels see it.  S is the pairwise-stage scalar (float or
 // double); coefficients, linear term, residuals and the boundary data are FP64.
@@ -172,7 +180,8 @@ struct mato_plan_s {
     int solve = MATO_SOLVE_DENSE;
     std::vector<double> Ks0, Ksn;  // structured solve: inverses of K_0 and K_{rho n}, (nv+6)^2 FP64
     double* dS = nullptr;        // structured solve: [nv][nv] M1, [nv][nv] M2, [nv][6] E0, [nv][6] En
-    unsigned* dPairs = nullptr;  // [n(n-1)/2 + n n_obs] row p -> i | j << 16 in the row order of A_fc
+    unsigned* dPairs = nullptr;  // [n(n-1)/2 + n n_obs] internal row -> i | j << 16 (i < j)
+    std::vector<unsigned> pairs; // host copy: the canonical row of internal row r is canonical_row(pairs[r])
     void* dAhi = nullptr;        // GEMM operand K11^{-1}: fp32, bf16 high term or fp64
     void* dAlo = nullptr;        // bf16 middle and low terms, one [Mp][ldk] plane each
     int ldk = 0;                 // padded row stride of the GEMM operand

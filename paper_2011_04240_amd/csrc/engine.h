@@ -415,9 +415,12 @@ struct Engine {
         }
     }
 
-    // LDS of the pairwise kernel per instant of a work item: the FP64 sum over agents of X,
-    // positions X and b_fc (or its corrections) and two flag words per 32 pairs
+    // LDS of the pairwise kernel per instant of a work item.  FP32: positions (x, y, z, 0)
+    // and the fixed-point corrections of the per-agent sums, 40 n bytes.  FP64: the FP64
+    // sum over agents of X, positions X and b_fc (or its corrections) and two flag words
+    // per 32 pairs.
     static size_t pairwise_lds_per_instant(const Prob& P) {
+        if (std::is_same<S, float>::value) return (size_t)40 * P.n;
         return (size_t)3 * sizeof(double) + (size_t)3 * (P.n + P.np) * sizeof(S) +
                (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
     }
@@ -921,7 +924,7 @@ struct Engine {
                     return MATO_OK;
                 }
         }
-        const int ipws[] = {512, 1024, 2048, 4096, 8192, 16384};
+        const int ipws[] = {512, 1024, 2048, 4096, 8192, 16384, 32768};
         const int thrs[] = {256, 512, 1024};
         float best = 1e30f;
         int bi = items_per_wg, bt = threads;

@@ -527,6 +527,322 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
     }
 }
 
+// ----------------------------------------------------------------------------------
+// The pairwise stage of FP32 problems, with the per-agent sums in fixed point.
+//
+// S_i(t) = sum_{j>i} b_ij - sum_{j<i} b_ji + sum_o (x_o + b_io).  With every b written as
+// delta + corr (delta = X_i - X_j, or X_i - x_o on an obstacle row; corr = b - delta):
+//     S_i = (n + n_obs) X_i - sum_j X_j + sum over the rows of agent i of (+-corr),
+// + where i is the row's first member, - where it is the second.  The positions and the
+// corrections enter in fixed point with kFx fractional bits (int64): those sums are exact,
+// so the rows' corrections can be added with LDS atomics in whatever order the lanes reach
+// them and S_i does not depend on the tile shape or the batch.  S_i is rounded to FP32
+// once.  A row whose corr is +0 on every axis (b = delta: the usual case away from
+// collisions) adds nothing.  The rows come in the plan's tournament order, so the lanes
+// of a wavefront touch different agents and the atomics rarely collide.
+//
+// LDS per instant of the work item: the positions [n] (x, y, z, 0) and the corrections
+// [3][n] (int64), 40 n bytes; then the obstacle table.  Thread layout, multiplier
+// loads and the far-pair shortcut are those of pairwise_kernel.
+constexpr int kFx = 40;
+
+// round(v 2^kFx) as an int64 (|v| < 2^22): the double y is exact, hi and lo are its
+// upper and lower 32 bits.
+__device__ inline long long fx_of(float v) {
+    const double y = rint(ldexp((double)v, kFx));
+    const double hi = floor(y * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, y);
+    const unsigned long long u = ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+    return (long long)u;
+}
+
+template <int BLOCK, int MODE, bool OBS>
+__global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __restrict__ items,
+                                                            const ProblemDesc<float>* __restrict__ probs) {
+    using S = float;
+    constexpr int U = 4;
+    const WorkItem it = items[blockIdx.x];
+    const ProblemDesc<S>* __restrict__ Dp = probs + it.prob;
+    gptr<const int> ctrl = glob((const int*)Dp->ctrl);
+    if (!ctrl[3]) return;                          // inactive slot
+    if (MODE == kModeIter && ctrl[1]) return;      // converged
+    const int n = Dp->n, np = Dp->np, n_obs = OBS ? Dp->n_obs : 0;
+    const int t0 = it.t0, tc = it.tc;
+    gptr<const S> Xm = glob((const S*)Dp->X);
+    gptr<const unsigned> pairs = glob(Dp->pairs);
+    gptr<S> lam = glob(Dp->lam);
+    gptr<S> ssum = glob(Dp->ssum);
+    gptr<const S> proj_in = glob(Dp->proj_in);
+    S* const dbg_proj_p = Dp->dbg_proj;
+    S* const dbg_d_p = Dp->dbg_d;
+    const bool dbg_on = dbg_proj_p != nullptr || dbg_d_p != nullptr;
+    gptr<double> part = glob(Dp->part);
+    const S ia2 = Dp->ia2, ib2 = Dp->ib2, rho = Dp->srho, irho = Dp->sirho, lzl = Dp->lz;
+    const bool shifted = Dp->shifted != 0;
+    // b_fc feeds the next x-step, which uses the next stage's rho on a stage's last iteration
+    const S irho_b = (MODE == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->sirho_next : irho;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
+    long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n]
+    S* Os = reinterpret_cast<S*>(Acc + (size_t)tc * 3 * n);              // [n_obs][kObs]
+    __shared__ int any_general;                    // some row took the general branch (iteration)
+    const int tid = threadIdx.x;
+
+    int pw = 64;
+    while (pw < np && pw < BLOCK) pw <<= 1;
+    const int tg = BLOCK / pw;
+    const int pl = tid & (pw - 1);
+    const int tgid = __builtin_amdgcn_readfirstlane(tid / pw);          // wavefront-uniform
+    const int ntl = (tgid < tc) ? (tc - tgid + tg - 1) / tg : 0;
+    const int npb = (np + pw * U - 1) / (pw * U);
+    const int nit = npb * ntl;
+    const size_t first0 = (size_t)(t0 + tgid) * 3 * np;
+    const size_t istride = (size_t)tg * 3 * np;
+    const int cstride = pw * U;
+    auto rsrc_at = [&](size_t first, int kc) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(S*)(lam + first), (short)0,
+                                                 (3 * np - kc * cstride) * (int)sizeof(S), 0x00020000);
+    };
+    const int axis_bytes = np * (int)sizeof(S);
+    const unsigned lane_bytes = (unsigned)pl * sizeof(S);
+
+    unsigned code[U];
+    S L[U][3], Q[U][3];
+    auto fetch = [&](int kc, int ki, size_t first) {
+        const int pb = kc * cstride;
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(first, kc);
+        if (ki == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) code[u] = pairs[min(pb + u * pw + pl, np - 1)];   // past np: unused
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = pb + u * pw + pl;
+            const bool ok = p < np;
+            if (MODE != kModeInit) {
+                const unsigned vo = ok ? lane_bytes : kOutOfRange;   // past the last row: 0
+                const int so = u * pw * (int)sizeof(S);
+                L[u][0] = Buf<S>::load(rs, vo, so);
+                L[u][1] = Buf<S>::load(rs, vo, so + axis_bytes);
+                L[u][2] = Buf<S>::load(rs, vo, so + 2 * axis_bytes);
+            } else {
+                L[u][0] = L[u][1] = L[u][2] = 0;
+            }
+            if (MODE == kModeSetState) {
+                Q[u][0] = Q[u][1] = Q[u][2] = 0;
+                if (ok) {
+                    const size_t e = first + (size_t)(u * pw + pl);
+                    Q[u][0] = proj_in[e];
+                    Q[u][1] = proj_in[e + np];
+                    Q[u][2] = proj_in[e + 2 * (size_t)np];
+                }
+            }
+        }
+    };
+    if (nit > 0) fetch(0, 0, first0);
+
+    if (n_obs > 0) {
+        gptr<const S> og = glob(Dp->obs);
+        for (int idx = tid; idx < n_obs * kObs; idx += BLOCK) Os[idx] = og[idx];
+    }
+    {
+        gptr<const S> Xg = Xm + (size_t)t0 * 3 * n;            // X [t][3][n] -> Xs [t][n] (x, y, z, 0)
+        for (int idx = tid; idx < tc * n; idx += BLOCK) {
+            const int tl = idx / n, i = idx - tl * n;
+            gptr<const S> xg = Xg + (size_t)tl * 3 * n + i;
+            Xs[idx] = make_float4(xg[0], xg[n], xg[2 * n], 0.f);
+        }
+        for (int idx = tid; idx < tc * 3 * n; idx += BLOCK) Acc[idx] = 0;
+        if (tid == 0) any_general = 0;
+    }
+    __syncthreads();
+
+    S rmax = 0, rsum = 0;
+    bool general = false;
+    int kc = 0, ki = 0;
+    size_t f_cur = first0, c_first = first0;
+    for (int k = 0; k < nit; ++k) {
+        unsigned cc[U];
+        S Lc[U][3], Qc[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cc[u] = code[u];
+            Lc[u][0] = L[u][0]; Lc[u][1] = L[u][1]; Lc[u][2] = L[u][2];
+            if (MODE == kModeSetState) { Qc[u][0] = Q[u][0]; Qc[u][1] = Q[u][1]; Qc[u][2] = Q[u][2]; }
+        }
+        int kc1 = kc, ki1 = ki + 1;
+        size_t f_nxt = f_cur + istride, c_nxt = c_first;
+        if (ki1 == ntl) {
+            ki1 = 0;
+            ++kc1;
+            c_nxt = c_first + cstride;
+            f_nxt = c_nxt;
+        }
+        if (k + 1 < nit) fetch(kc1, ki1, f_nxt);
+        const int pb = kc * cstride;
+        const int tl = tgid + ki * tg;
+        const size_t fc = f_cur;
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(f_cur, kc);
+        kc = kc1;
+        ki = ki1;
+        f_cur = f_nxt;
+        c_first = c_nxt;
+        const float4* X = Xs + (size_t)tl * n;
+        long long* A = Acc + (size_t)tl * 3 * n;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = pb + u * pw + pl;
+            if (p >= np) continue;
+            const S lx = Lc[u][0], ly = Lc[u][1], lzm = Lc[u][2];
+            const int i = (int)(cc[u] & 0xffffu), j = (int)(cc[u] >> 16);
+            const float4 xi = X[i];
+            S xj, yj, zj, ia2p = ia2, ib2p = ib2, lzp = lzl;
+            if (!OBS || j < n) {
+                const float4 xv = X[j];
+                xj = xv.x;
+                yj = xv.y;
+                zj = xv.z;
+            } else {
+                const S* ob = Os + (j - n) * kObs;
+                xj = ob[0];
+                yj = ob[1];
+                zj = ob[2];
+                ia2p = ob[3];
+                ib2p = ob[4];
+                lzp = ob[5];
+            }
+            const S dx = xi.x - xj;
+            const S dy = xi.y - yj;
+            const S dz = xi.z - zj;
+            // b_fc - delta of this row into the agent sums (+ for i, - for an agent j)
+            auto record = [&](S cx, S cy, S cz) {
+                if ((bits_of(cx) | bits_of(cy) | bits_of(cz)) == 0) return;
+                const long long fx = fx_of(cx), fy = fx_of(cy), fz = fx_of(cz);
+                atomicAdd((unsigned long long*)&A[i], (unsigned long long)fx);
+                atomicAdd((unsigned long long*)&A[n + i], (unsigned long long)fy);
+                atomicAdd((unsigned long long*)&A[2 * n + i], (unsigned long long)fz);
+                if (!OBS || j < n) {
+                    atomicAdd((unsigned long long*)&A[j], (unsigned long long)(-fx));
+                    atomicAdd((unsigned long long*)&A[n + j], (unsigned long long)(-fy));
+                    atomicAdd((unsigned long long*)&A[2 * n + j], (unsigned long long)(-fz));
+                }
+            };
+            if (MODE == kModeSetState) {
+                record(Qc[u][0] - lx * irho - dx, Qc[u][1] - ly * irho - dy, Qc[u][2] - lzm * irho - dz);
+                continue;
+            }
+            const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+            // no multiplier (+0) and clear of the collision set by a margin: the general branch
+            // gives w = 1, d e = delta, f_c = +0, lambda = +0 (not stored), b_fc = delta (no
+            // correction) and a zero residual, bit for bit
+            const bool clear = (q2 > S(1.0001)) & ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0);
+            const bool fast = (MODE == kModeIter) & !shifted & !dbg_on & clear;
+            if (fast) continue;
+            S px, py, pz, dd;
+            if (!shifted) {
+                if (q2 > 0) {
+                    const S D2 = dx * dx + dy * dy + dz * dz;
+                    const S rs_ = Recip<S>::rsq(q2);                    // 1 / s
+                    const S dl = dx * lx + dy * ly + dz * lzm;
+                    const S w = fmax(rs_, S(1) + dl * irho * Recip<S>::rcp(D2));
+                    px = w * dx;
+                    py = w * dy;
+                    pz = w * dz;
+                    dd = w * (q2 * rs_);                                // d = w s
+                } else {                                                // delta = 0: e = (0, 0, l_z)
+                    dd = fmax(S(1), lzm * irho / lzp);
+                    px = 0;
+                    py = 0;
+                    pz = dd * lzp;
+                }
+            } else {
+                // variant: project v = delta + lambda/rho; then d = max(1, s_v), d e = max(1/s_v, 1) v
+                const S vx = dx + lx * irho, vy = dy + ly * irho, vz = dz + lzm * irho;
+                const S q2v = (vx * vx + vy * vy) * ia2p + vz * vz * ib2p;
+                if (q2v > 0) {
+                    const S rs_ = Recip<S>::rsq(q2v);
+                    const S w = fmax(rs_, S(1));
+                    px = w * vx;
+                    py = w * vy;
+                    pz = w * vz;
+                    dd = w * (q2v * rs_);
+                } else {                                                // v = 0: e = (0, 0, l_z), d = 1
+                    dd = S(1);
+                    px = 0;
+                    py = 0;
+                    pz = lzp;
+                }
+            }
+            const S fx_ = dx - px, fy_ = dy - py, fz_ = dz - pz;
+            S nlx = 0, nly = 0, nlz = 0;
+            if (MODE == kModeIter) {
+                nlx = lx + rho * fx_;
+                nly = ly + rho * fy_;
+                nlz = lzm + rho * fz_;
+                const S fn2 = fx_ * fx_ + fy_ * fy_ + fz_ * fz_;
+                rmax = fmax(rmax, fn2);
+                rsum += fn2;
+                general = true;
+            }
+            // an iteration stores only the multipliers whose bits change
+            const int so = u * pw * (int)sizeof(S);
+            if (MODE != kModeIter || bits_of(nlx) != bits_of(lx)) Buf<S>::store(nlx, rs, lane_bytes, so);
+            if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) Buf<S>::store(nly, rs, lane_bytes, so + axis_bytes);
+            if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
+                Buf<S>::store(nlz, rs, lane_bytes, so + 2 * axis_bytes);
+            record(px - nlx * irho_b - dx, py - nly * irho_b - dy, pz - nlz * irho_b - dz);
+            if (dbg_on) {
+                const size_t e = fc + (size_t)(u * pw + pl);          // (t0 + tl) 3 np + p
+                if (dbg_proj_p) {
+                    gptr<S> dp = glob(dbg_proj_p);
+                    dp[e] = px;
+                    dp[e + np] = py;
+                    dp[e + 2 * (size_t)np] = pz;
+                }
+                if (dbg_d_p) glob(dbg_d_p)[(size_t)(t0 + tl) * np + p] = dd;
+            }
+        }
+    }
+    if (MODE == kModeIter && general) any_general = 1;
+    __syncthreads();
+
+    // S_i = (n + n_obs) X_i - sum_j X_j + corrections, per (instant, axis) row by one
+    // wavefront: the agent sum as an exact int64 butterfly, every lane with the same value
+    const int nn = n + n_obs;
+    const int wv = tid >> 6, lane = tid & 63;
+    for (int r = wv; r < tc * 3; r += BLOCK / 64) {
+        const int tl = r / 3, a = r - tl * 3;
+        const float* Xr = reinterpret_cast<const float*>(Xs + (size_t)tl * n) + a;   // stride 4
+        long long sx = 0;
+        for (int j = lane; j < n; j += 64) sx += fx_of(Xr[4 * j]);
+        for (int off = 32; off > 0; off >>= 1) sx += __shfl_xor(sx, off);
+        const long long* Ar = Acc + (size_t)r * n;
+        gptr<S> out = ssum + ((size_t)(t0 + tl) * 3 + a) * n;
+        for (int i = lane; i < n; i += 64) {
+            const long long v = (long long)nn * fx_of(Xr[4 * i]) - sx + Ar[i];
+            out[i] = (S)ldexp((double)v, -kFx);
+        }
+    }
+
+    if (MODE == kModeIter) {
+        __shared__ double red[2 * (BLOCK / 64)];
+        if (any_general) {                          // uniform: read after the barrier
+            double s1 = (double)rsum;
+            const double mx = block_reduce_max_sum<S, BLOCK>(rmax, s1, red);
+            if (tid == 0) {
+                gptr<double> pp = part + (size_t)it.slab * 4;
+                pp[0] = mx;
+                pp[1] = s1;
+            }
+        } else if (tid == 0) {                      // every row took the shortcut: zero residual
+            gptr<double> pp = part + (size_t)it.slab * 4;
+            pp[0] = 0.0;
+            pp[1] = 0.0;
+        }
+    }
+}
+
 // One workgroup per problem: X = P c (eq. (param)) at every instant, in FP64 products
 // stored as S, and the smoothness cost sum (Pddot c)^2 of eq. (cost_proposed).  A
 // thread owns (axis, agent) columns; the basis rows are staged in LDS in chunks of
@@ -951,13 +1267,40 @@ static hipError_t launch_pw_mode(const WorkItem* items, int nitems, const Proble
     return launch_pw<S, NV, kModeSetState, true>(items, nitems, probs, threads, lds, st);
 }
 
+template <int MODE, bool OBS>
+static hipError_t launch_fx(const WorkItem* items, int nitems, const ProblemDesc<float>* probs, int threads,
+                            size_t lds, hipStream_t st) {
+    switch (threads) {
+        case 256:
+            pairwise_fx_kernel<256, MODE, OBS><<<nitems, 256, lds, st>>>(items, probs);
+            break;
+        case 512:
+            pairwise_fx_kernel<512, MODE, OBS><<<nitems, 512, lds, st>>>(items, probs);
+            break;
+        default:
+            pairwise_fx_kernel<1024, MODE, OBS><<<nitems, 1024, lds, st>>>(items, probs);
+            break;
+    }
+    return hipGetLastError();
+}
+
 // nv: the (common) number of basis coefficients of the launch's problems, or 0 if they differ.
+// FP32 problems take the fixed-point kernel, FP64 problems the direct one.
 template <typename S>
 hipError_t launch_pairwise(const WorkItem* items, int nitems, const ProblemDesc<S>* probs, int mode,
                            int threads, size_t lds, int nv, bool obs, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, obs, threads, lds, st);
-    return launch_pw_mode<S, 0>(items, nitems, probs, mode, obs, threads, lds, st);
+    if constexpr (std::is_same<S, float>::value) {
+        (void)nv;
+        if (mode == kModeIter)
+            return obs ? launch_fx<kModeIter, true>(items, nitems, probs, threads, lds, st)
+                       : launch_fx<kModeIter, false>(items, nitems, probs, threads, lds, st);
+        if (mode == kModeInit) return launch_fx<kModeInit, true>(items, nitems, probs, threads, lds, st);
+        return launch_fx<kModeSetState, true>(items, nitems, probs, threads, lds, st);
+    } else {
+        if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, obs, threads, lds, st);
+        return launch_pw_mode<S, 0>(items, nitems, probs, mode, obs, threads, lds, st);
+    }
 }
 
 template <typename S, int NV, int MODE, bool OBS>
@@ -983,11 +1326,33 @@ static hipError_t set_lds_nv(size_t lds) {
     return set_lds_one<S, NV, kModeSetState, true>(lds);
 }
 
+template <int MODE, bool OBS>
+static hipError_t set_lds_fx(size_t lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<256, MODE, OBS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<512, MODE, OBS>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)pairwise_fx_kernel<1024, MODE, OBS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename S>
 hipError_t set_pairwise_lds_limit(size_t lds) {
-    hipError_t e = set_lds_nv<S, 11>(lds);
-    if (e != hipSuccess) return e;
-    return set_lds_nv<S, 0>(lds);
+    if constexpr (std::is_same<S, float>::value) {
+        hipError_t e = set_lds_fx<kModeIter, false>(lds);
+        if (e != hipSuccess) return e;
+        e = set_lds_fx<kModeIter, true>(lds);
+        if (e != hipSuccess) return e;
+        e = set_lds_fx<kModeInit, true>(lds);
+        if (e != hipSuccess) return e;
+        return set_lds_fx<kModeSetState, true>(lds);
+    } else {
+        hipError_t e = set_lds_nv<S, 11>(lds);
+        if (e != hipSuccess) return e;
+        return set_lds_nv<S, 0>(lds);
+    }
 }
 
 template <typename S>

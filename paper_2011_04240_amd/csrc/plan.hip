@@ -322,11 +322,37 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         p0->A[4 * nv + j] = p0->Pd[(size_t)(T - 1) * nv + j];
         p0->A[5 * nv + j] = p0->Pdd[(size_t)(T - 1) * nv + j];
     }
+    // Internal order of the collision rows (the layout of the multipliers on the device).
+    // FP64 plans: the canonical order, pairs in the row order of A_fc, then agent-obstacle
+    // rows agent-major.  FP32 / BF16 plans: the pairs in the rounds of a round-robin
+    // tournament (circle method: with m = n rounded up to even, round r pairs agent m - 1
+    // with r and (r + k) mod (m - 1) with (r - k) mod (m - 1), k = 1 .. m/2 - 1; pairs with
+    // the ghost agent of an odd n are left out), so that neighbouring rows, which
+    // neighbouring lanes of a wavefront process, involve different agents; then the
+    // obstacle rows obstacle-major.  Every entry keeps its smaller agent first (delta =
+    // X_i - X_j, i < j, whatever the order of the rows).
     std::vector<unsigned> pairs;
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j) pairs.push_back((unsigned)i | ((unsigned)j << 16));
-    for (int i = 0; i < n; ++i)                  // agent-obstacle rows: partner n + o
-        for (int o = 0; o < p0->n_obs; ++o) pairs.push_back((unsigned)i | ((unsigned)(n + o) << 16));
+    auto add = [&](int i, int j) {
+        if (i > j) std::swap(i, j);
+        pairs.push_back((unsigned)i | ((unsigned)j << 16));
+    };
+    if (p0->precision == MATO_FP64) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) add(i, j);
+        for (int i = 0; i < n; ++i)
+            for (int o = 0; o < p0->n_obs; ++o) add(i, n + o);
+    } else {
+        const int m = n + (n & 1);
+        for (int r = 0; r < m - 1; ++r) {
+            if (m - 1 < n) add(m - 1, r);             // agent m - 1 exists when n is even
+            for (int k = 1; k < m / 2; ++k) {
+                const int a = (r + k) % (m - 1), b = (r - k + (m - 1)) % (m - 1);
+                if (a < n && b < n) add(a, b);
+            }
+        }
+        for (int o = 0; o < p0->n_obs; ++o)
+            for (int i = 0; i < n; ++i) add(i, n + o);
+    }
     for (auto p : ps) {
         if (p != p0) {
             p->P = p0->P; p->Pd = p0->Pd; p->Pdd = p0->Pdd;
@@ -338,6 +364,7 @@ static mato_status plans_build(std::vector<mato_plan>& ps) {
         MATO_TRY(upload(&p->dPddtPdd, p->PddtPdd, &p->bytes));
         MATO_TRY(upload(&p->dA, p->A, &p->bytes));
         MATO_TRY(upload(&p->dPairs, pairs, &p->bytes));
+        p->pairs = pairs;
     }
 
     // Per-agent KKT matrices K_sigma = [[Pdd^T Pdd + sigma P^T P, A^T], [A, 0]].  K_0 is the
