@@ -8,18 +8,20 @@ With `--streams S` the B problems are split into S batches on their own streams,
 stepped together (one batch's pairwise stage beside the other's per-problem
 kernels); the step as one batch on one stream is the default.
 
-Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step),
-the roofline of the pairwise kernel (12 algorithmic bytes per pair-instant: the
-FP32 multipliers read; a multiplier is written back only where its value changes,
-which is rare: 24 bytes per pair-instant, every multiplier read and written back,
-is reported beside it), timed with HIP events on the stream of
-the single batch of all B problems, and the FP64 oracle timed on the host on a
-bounded sample.  Also in the
-line: the same step with the structured x/y/z solve, served p50/p99 solve latency
-of a short Poisson trace through the continuous-batching server (agent counts
-4..128), uneven-size batching (256 problems, n in {8, 12, ..., 48}) against the
-same problems solved one at a time, and the iteration time against the number of
-static obstacles (16 agents).  `--serve-sweep` replaces all of this by the latency sweep over arrival rates.
+Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step), the
+roofline of the pairwise kernel on the method's 24 bytes per pair-instant (every
+FP32 multiplier read and written back; the kernel writes back only the multipliers
+that change, so the line also gives the share of pair-instants that take the far-pair
+shortcut and of multipliers rewritten, the calibrated HBM counter bytes and their
+rate, and the multiplier reads against a measured streaming read), timed with HIP
+events on the stream of the batch, and the FP64 oracle timed on the host on a
+bounded sample (pool aggregate, and one problem on one thread).  Also in the line:
+the same iteration on crowded, packed and n = 128 scenes, the structured x/y/z
+solve, served p50/p99 of the serving configuration (dense BF16 product with FP64
+corrections, n in 4..128, 10 / 100 / 500 requests/s) and of the structured variant,
+uneven-size batching (256 problems, n in {8, 12, ..., 48}) against the same problems
+solved one at a time, and the iteration time against the number of static obstacles
+(16 agents).  `--serve-sweep` replaces all of this by the latency sweep over arrival rates.
 """
 import argparse
 import hashlib
