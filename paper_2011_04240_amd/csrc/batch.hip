@@ -25,8 +25,12 @@ static mato_status batch_create(int count, const mato_plan* plans, const double*
     B->precision = plans[0]->precision;
     B->solve = plans[0]->solve;
     B->refine = (B->precision == MATO_FP32) ? 1 : (B->precision == MATO_BF16_REFINED ? 2 : 0);
-    if (const char* e = getenv("MATO_REFINE")) B->refine = std::max(0, std::min(kMaxRefine, atoi(e)));
+    if (const char* e = getenv("MATO_REFINE")) {
+        B->refine = std::max(0, std::min(kMaxRefine, atoi(e)));
+        B->refine_fixed = true;
+    }
     if (B->solve == MATO_SOLVE_STRUCTURED) B->refine = 0;     // the structured step is FP64 throughout
+    B->refine_base = B->refine;
     B->stream = st;
     auto fail = [&](mato_status s) { delete B; return s; };
     int agents = 0, nobs = 0;

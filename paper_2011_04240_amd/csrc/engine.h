@@ -112,7 +112,13 @@ struct Engine {
 
     int precision = MATO_FP32;
     int solve = MATO_SOLVE_DENSE;            // every plan of the engine has this solve kind
-    int refine = 1;
+    int refine = 1;                          // FP64 corrections after the inverse product
+    int refine_base = 1;                     // the precision's default
+    bool refine_fixed = false;               // set by MATO_REFINE: no adaptation
+    // The FP32 correction contracts by about u kappa per pass and kappa grows with rho (n + n_obs):
+    // from this product on, FP32 batches take one more correction (the ten-rho schedule to 512 left
+    // 32-agent swaps and one of six 128-agent boxes at the iteration cap with one correction)
+    static constexpr double kRefineRhoN = 4096.0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     std::vector<Prob> probs;                 // slots
@@ -460,6 +466,11 @@ struct Engine {
             if (!probs[q].active || solve == MATO_SOLVE_STRUCTURED) continue;
             if (!members.count(probs[q].plan)) order.push_back(probs[q].plan);
             members[probs[q].plan].push_back(q);
+        }
+        if (!refine_fixed && precision == MATO_FP32 && solve == MATO_SOLVE_DENSE) {
+            refine = refine_base;
+            for (const mato_plan pl : order)
+                if (pl->rho * (double)(pl->n + pl->n_obs) >= kRefineRhoN) refine = refine_base + 1;
         }
         std::vector<GemmCol> colq, colr;
         hgroups.clear();

@@ -289,9 +289,13 @@ struct ServerOps {
         s->eng = e;
         e->precision = s->cfg.precision;
         e->refine = (e->precision == MATO_FP32) ? 1 : (e->precision == MATO_BF16_REFINED ? 2 : 0);
-        if (const char* v = getenv("MATO_REFINE")) e->refine = std::max(0, std::min(kMaxRefine, atoi(v)));
+        if (const char* v = getenv("MATO_REFINE")) {
+            e->refine = std::max(0, std::min(kMaxRefine, atoi(v)));
+            e->refine_fixed = true;
+        }
         e->solve = s->cfg.solve;
         if (e->solve == MATO_SOLVE_STRUCTURED) e->refine = 0;
+        e->refine_base = e->refine;
         e->stream = s->stream;
         e->tol = s->cfg.tol;
         MATO_TRY(e->init_capacity(s->cfg.max_slots));
