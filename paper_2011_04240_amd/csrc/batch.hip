@@ -257,6 +257,10 @@ static mato_status get_state_impl(BatchImpl<S>* B, int q, void* c, void* lambda,
         MATO_TRY(copy_out(d, o.data(), sizeof(S) * npt));
     }
     if (X) {
+        // FP32 iterations keep the positions in LDS only: form X = P c of the current
+        // coefficients here (the same FP64 products, rounded once)
+        MATO_HIP(launch_positions<S>(B->ddesc + q, 1, kModeInit, P.nv == 11 ? 11 : 0, B->stream));
+        MATO_HIP(hipStreamSynchronize(B->stream));
         const size_t nx = (size_t)P.n * 3 * P.T;
         std::vector<S> h(nx), o(nx);
         MATO_HIP(hipMemcpy(h.data(), D.X, sizeof(S) * nx, hipMemcpyDeviceToHost));

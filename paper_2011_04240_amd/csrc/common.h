@@ -112,7 +112,7 @@ struct ProblemDesc {
     S* lam;                     // [T][3][np] multipliers
     S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
     S* X;                       // [T][3][n]  positions P c of the current coefficients
-    double* misc;               // [4]        [0] smoothness cost of the current coefficients
+    double* misc;               // [4]        reserved
     double* c;                  // [3][ldc]   coefficients (agent-major per axis)
     double* ceq;                // [3][ldc]   c_eq = K12^{-1} b_eq (boundary part of the product)
     double* q;                  // [3][ldq]   [rho A_fc^T b_fc ; b_eq]  (eq. kkt_step_x)
@@ -133,6 +133,18 @@ struct ProblemDesc {
     S* dbg_d;                   // [T][np]
     const S* proj_in;           // set-state input [T][3][np]
 };
+
+// Workgroups of a launch are dealt to the device's 8 accelerator dies (XCDs), each with
+// its own L2, round-robin by workgroup index (blockIdx mod 8).  xcd_tile maps workgroup b
+// to list entry start(b mod 8) + b / 8, so each die works through one contiguous run of
+// the list (a bijection for any list length): neighbouring entries that read the same
+// data fetch it into one L2 instead of eight.
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int b, int ntiles) {
+    const int q = ntiles / kXcds, r = ntiles % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + min(x, r) + j;
+}
 
 struct WorkItem {               // one pairwise workgroup: instants [t0, t0 + tc) of problem `prob`
     int prob, t0, tc, slab;

@@ -3,9 +3,10 @@
 //
 //   [inverse product]   c = c_eq + K11^{-1} g                     (eq. (kkt_step_x))
 //   [refinement x R]    r = g - H c (FP64);  c += K11^{-1} r
-//   [positions]         X = P c, smoothness cost                  (eq. (param))
+//   [positions]         X = P c                                   (eq. (param); FP32: inside the pairwise launch)
 //   [pairwise]          delta; alpha, beta; d; lambda; b_fc; S    (eqs. (sphere_project)-(lag_update), (b_f))
-//   [linear term]       g = rho P^T S = rho A_fc^T b_fc; residual record; convergence test
+//   [linear term]       g = rho P^T S = rho A_fc^T b_fc; residual record with the
+//                       smoothness cost; convergence test
 //
 // Active slots with the same plan form one group whose right-hand sides are the
 // columns of one matrix-matrix product; all pairwise work of all active slots is
@@ -421,12 +422,12 @@ struct Engine {
         }
     }
 
-    // LDS of the pairwise kernel per instant of a work item.  FP32: positions (x, y, z, 0)
-    // and the fixed-point corrections of the per-agent sums, 40 n bytes.  FP64: the FP64
-    // sum over agents of X, positions X and b_fc (or its corrections) and two flag words
-    // per 32 pairs.
+    // LDS of the pairwise kernel per instant of a work item.  FP32: positions (x, y, z, 0),
+    // 16 n bytes, and the fixed-point corrections of the per-agent sums, 24 n bytes, an area
+    // that first holds the basis row (8 n_v bytes).  FP64: the FP64 sum over agents of X,
+    // positions X and b_fc (or its corrections) and two flag words per 32 pairs.
     static size_t pairwise_lds_per_instant(const Prob& P) {
-        if (std::is_same<S, float>::value) return (size_t)40 * P.n;
+        if (std::is_same<S, float>::value) return (size_t)16 * P.n + std::max((size_t)24 * P.n, (size_t)8 * P.nv);
         return (size_t)3 * sizeof(double) + (size_t)3 * (P.n + P.np) * sizeof(S) +
                (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
     }
@@ -709,8 +710,10 @@ struct Engine {
                 e = launch_gemm(precision, gemm_width, dtiles, (int)htiles.size(), dgroups, dcolsr, 1, st);
                 if (e != hipSuccess) return e;
             }
-            e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);
-            if (e != hipSuccess) return e;
+            if constexpr (!std::is_same<S, float>::value) {     // FP32: the pairwise kernel forms X
+                e = launch_positions<S>(ddesc, count(), kModeIter, nv, st);
+                if (e != hipSuccess) return e;
+            }
         }
         if (events) {
             while ((int)pw_events.size() < pw_used + 2) {

@@ -30,17 +30,9 @@ __device__ inline unsigned short f2bf_rne(float x) {
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (blockIdx mod 8), each XCD with
-// its own L2.  The tile list holds the 64-row tiles of one 64-column block consecutively,
-// so workgroup b takes tile start(b mod 8) + b / 8: each XCD gets a contiguous run of
-// tiles and the right-hand sides of a column block are fetched into one L2 instead of
-// eight.  A bijection for any tile count.
-constexpr int kXcds = 8;
-__device__ inline int xcd_tile(int b, int ntiles) {
-    const int q = ntiles / kXcds, r = ntiles % kXcds;
-    const int x = b % kXcds, j = b / kXcds;
-    return x * q + min(x, r) + j;
-}
+// The tile list holds the 64-row tiles of one 64-column block consecutively and workgroups
+// take tiles through xcd_tile: the right-hand sides of a column block are fetched into one
+// L2 instead of eight.
 
 struct TileCols {
     const double* bptr;

@@ -7,11 +7,13 @@
 //                    next x/y/z step, and the per-agent sums
 //                    S_i(t) = sum_{j>i} b_ij(t) - sum_{j<i} b_ji(t)
 //                    that A_fc^T b reduces to before the factor P^T.
-//   positions_kernel X = P c at every instant and the smoothness cost, once per problem.
+//   positions_kernel X = P c at every instant, once per problem (FP64 problems and
+//                    initialisation; the FP32 pairwise kernel forms X itself).
 //   solve_positions_kernel  the x/y/z step from the two per-agent inverses of the
-//                    structured solve, then what positions_kernel does.
+//                    structured solve, then (FP64) what positions_kernel does.
 //   qbuild_kernel    g = rho A_fc^T b_fc = rho P^T S_i (FP64), plus the iteration's
-//                    residual record and the convergence test.
+//                    residual record (max ||f_c||, rms, smoothness cost) and the
+//                    convergence test.
 //   residual_kernel  FP64 refinement residual g - H c of eq. (kkt_step_x), with
 //                    H c = (I (x) Pdd^T Pdd) c + rho (((n + n_obs) I - 1 1^T) (x) P^T P) c.
 //   ceq_kernel       c_eq = K12^{-1} b_eq, the boundary part of the inverse product.
@@ -541,8 +543,13 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
 // collisions) adds nothing.  The rows come in the plan's tournament order, so the lanes
 // of a wavefront touch different agents and the atomics rarely collide.
 //
+// The positions of the work item's instants are formed here from the current
+// coefficients (X = P c in FP64, eq. (param)), so an FP32 iteration has no positions
+// launch and no positions traffic; the X buffer is filled only when it is read back.
+//
 // LDS per instant of the work item: the positions [n] (x, y, z, 0) and the corrections
-// [3][n] (int64), 40 n bytes; then the obstacle table.  Thread layout, multiplier
+// [3][n] (int64), 40 n bytes (at least 16 n + 8 n_v: the corrections' area holds the
+// basis rows first); then the obstacle table.  Thread layout, multiplier
 // loads and the far-pair shortcut are those of pairwise_kernel.
 constexpr int kFx = 40;
 
@@ -556,19 +563,20 @@ __device__ inline long long fx_of(float v) {
     return (long long)u;
 }
 
-template <int BLOCK, int MODE, bool OBS>
+template <int BLOCK, int NV, int MODE, bool OBS>
 __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __restrict__ items,
                                                             const ProblemDesc<float>* __restrict__ probs) {
     using S = float;
     constexpr int U = 4;
-    const WorkItem it = items[blockIdx.x];
+    // a problem's items are consecutive in the list: through xcd_tile they run on one die,
+    // whose L2 then holds the problem's coefficients for all of them
+    const WorkItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
     const ProblemDesc<S>* __restrict__ Dp = probs + it.prob;
     gptr<const int> ctrl = glob((const int*)Dp->ctrl);
     if (!ctrl[3]) return;                          // inactive slot
     if (MODE == kModeIter && ctrl[1]) return;      // converged
     const int n = Dp->n, np = Dp->np, n_obs = OBS ? Dp->n_obs : 0;
     const int t0 = it.t0, tc = it.tc;
-    gptr<const S> Xm = glob((const S*)Dp->X);
     gptr<const unsigned> pairs = glob(Dp->pairs);
     gptr<S> lam = glob(Dp->lam);
     gptr<S> ssum = glob(Dp->ssum);
@@ -584,8 +592,9 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
-    long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n]
-    S* Os = reinterpret_cast<S*>(Acc + (size_t)tc * 3 * n);              // [n_obs][kObs]
+    const int nv = NV > 0 ? NV : Dp->nv;
+    long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n], first [tc][nv] doubles
+    S* Os = reinterpret_cast<S*>(Acc + (size_t)tc * max(3 * n, nv));     // [n_obs][kObs]
     __shared__ int any_general;                    // some row took the general branch (iteration)
     const int tid = threadIdx.x;
 
@@ -647,12 +656,52 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         for (int idx = tid; idx < n_obs * kObs; idx += BLOCK) Os[idx] = og[idx];
     }
     {
-        gptr<const S> Xg = Xm + (size_t)t0 * 3 * n;            // X [t][3][n] -> Xs [t][n] (x, y, z, 0)
-        for (int idx = tid; idx < tc * n; idx += BLOCK) {
-            const int tl = idx / n, i = idx - tl * n;
-            gptr<const S> xg = Xg + (size_t)tl * 3 * n + i;
-            Xs[idx] = make_float4(xg[0], xg[n], xg[2 * n], 0.f);
+        // positions of the work item's instants from the current coefficients, eq. (param):
+        // X = P c in FP64 per (axis, agent) column (coefficients ascending), rounded to FP32,
+        // into LDS as (x, y, z, .) (not stored: a readback forms them anew).  The basis rows of the
+        // item's instants are staged in the correction area (zeroed afterwards); a column's
+        // coefficients sit in registers and G = BLOCK / 3n thread groups take every G-th
+        // instant, two instants' products in flight at a time.
+        gptr<const double> cm = glob((const double*)Dp->c);
+        gptr<const double> Pm = glob(Dp->P);
+        const int ldc = Dp->ldc;
+        double* Pl = reinterpret_cast<double*>(Acc);                    // [tc][nv]
+        for (int idx = tid; idx < tc * nv; idx += BLOCK) Pl[idx] = Pm[(size_t)t0 * nv + idx];
+        __syncthreads();
+        float* Xf = reinterpret_cast<float*>(Xs);
+        const int n3 = 3 * n;
+        const int G = max(1, BLOCK / n3);
+        for (int w = tid; w < n3 * G; w += BLOCK) {
+            const int g = w / n3, col = w - g * n3;
+            const int a = col / n, i = col - a * n;
+            gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * nv;
+            auto put = [&](int tl, double x) { Xf[((size_t)tl * n + i) * 4 + a] = (S)x; };
+            if constexpr (NV > 0) {
+                double cv[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) cv[k] = ci[k];
+                for (int tl = g; tl < tc; tl += 2 * G) {
+                    int tu[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) tu[u] = min(tl + u * G, tc - 1);   // past tc: not stored
+                    double x[2] = {0.0, 0.0};
+#pragma unroll
+                    for (int k = 0; k < NV; ++k)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) x[u] += Pl[tu[u] * NV + k] * cv[k];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (tl + u * G < tc) put(tl + u * G, x[u]);
+                }
+            } else {
+                for (int tl = g; tl < tc; tl += G) {
+                    double x = 0.0;
+                    for (int k = 0; k < nv; ++k) x += Pl[tl * nv + k] * ci[k];
+                    put(tl, x);
+                }
+            }
         }
+        __syncthreads();                                               // Pl is read before Acc is zeroed
         for (int idx = tid; idx < tc * 3 * n; idx += BLOCK) Acc[idx] = 0;
         if (tid == 0) any_general = 0;
     }
@@ -844,26 +893,18 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
 }
 
 // One workgroup per problem: X = P c (eq. (param)) at every instant, in FP64 products
-// stored as S, and the smoothness cost sum (Pddot c)^2 of eq. (cost_proposed).  A
-// thread owns (axis, agent) columns; the basis rows are staged in LDS in chunks of
-// 32 instants.
+// stored as S (FP64 problems; the FP32 pairwise kernel forms its own instants' positions).
+// A thread owns (axis, agent) columns; the basis rows are staged in LDS in chunks.
 template <typename S, int NV>
 __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
     const int n = Dp->n, nv = NV > 0 ? NV : Dp->nv, T = Dp->T, ldc = Dp->ldc;
     gptr<const double> Pm = glob(Dp->P);
-    gptr<const double> Gm = glob(Dp->PddtPdd);
     gptr<const double> cm = glob((const double*)Dp->c);
     gptr<S> Xm = glob(Dp->X);
     constexpr int kRows = 3072;                    // basis entries staged per chunk (24 KB)
     __shared__ double Ps[kRows];
-    __shared__ double G[kMaxCoef * kMaxCoef];      // Pddot^T Pddot
-    __shared__ double red[3 * 4];
     const int n3 = 3 * n;
     const int TC = kRows / nv;                     // instants per chunk (279 for 11 coefficients)
-    for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) G[e] = Gm[e];
-    // The smoothness cost sum_t (Pddot c)^2 of a column is the quadratic form
-    // c^T (Pddot^T Pddot) c: n_v^2 products per column instead of T n_v.
-    double cost = 0.0;
     for (int tb = 0; tb < T; tb += TC) {
         const int tn = min(TC, T - tb);
         __syncthreads();
@@ -876,15 +917,6 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
                 double cv[NV];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) cv[k] = ci[k];
-                if (tb == 0) {
-#pragma unroll 1
-                    for (int k = 0; k < NV; ++k) {
-                        double gk = 0.0;
-#pragma unroll
-                        for (int l = 0; l < NV; ++l) gk += G[k * NV + l] * cv[l];
-                        cost += ci[k] * gk;          // ci[k] == cv[k], read from memory (k not unrolled)
-                    }
-                }
                 int t = 0;
                 // four instants at a time: four independent FMA chains and their LDS reads
                 // in flight together
@@ -904,12 +936,6 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
                     Xm[(size_t)(tb + t) * n3 + col] = (S)x;
                 }
             } else {
-                if (tb == 0)
-                    for (int k = 0; k < nv; ++k) {
-                        double gk = 0.0;
-                        for (int l = 0; l < nv; ++l) gk += G[k * nv + l] * ci[l];
-                        cost += ci[k] * gk;
-                    }
                 for (int t = 0; t < tn; ++t) {
                     double x = 0.0;
                     for (int k = 0; k < nv; ++k) x += Ps[t * nv + k] * ci[k];
@@ -918,9 +944,6 @@ __device__ inline void positions_body(const ProblemDesc<S>* __restrict__ Dp) {
             }
         }
     }
-    double z0 = 0.0, z1 = 0.0;
-    block_reduce3<double, 256>(z0, cost, z1, red);
-    if (threadIdx.x == 0) glob(Dp->misc)[0] = cost;
 }
 
 template <typename S, int NV>
@@ -994,8 +1017,10 @@ __global__ __launch_bounds__(256) void solve_positions_kernel(const ProblemDesc<
         const size_t oc = (size_t)a * ldc + rem;
         c[oc] = ceq[oc] + h[a * nv + k] + v;
     }
-    __syncthreads();                       // c is read back by other threads of this workgroup
-    positions_body<S, NV>(Dp);
+    if constexpr (!std::is_same<S, float>::value) {
+        __syncthreads();                   // c is read back by other threads of this workgroup
+        positions_body<S, NV>(Dp);
+    }
 }
 
 // One workgroup per problem: g = rho P^T S (FP64) into q[a][0 .. n*nv) (and its FP32
@@ -1097,10 +1122,42 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
       }
     }
     if (mode == kModeIter) {
+        // The smoothness cost of eq. (cost_proposed) of the current coefficients:
+        // sum_t (Pddot c)^2 of a column is the quadratic form c^T (Pddot^T Pddot) c, n_v^2
+        // products per column instead of T n_v; columns strided per thread, then the tree.
+        __shared__ double G[kMaxCoef * kMaxCoef];
+        gptr<const double> Gm = glob(Dp->PddtPdd);
+        gptr<const double> cm = glob((const double*)Dp->c);
+        const int ldc = Dp->ldc;
+        for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) G[e] = Gm[e];
+        __syncthreads();
+        double z = 0.0;
+        for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+            const int a = col / n, i = col - a * n;
+            gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * nv;
+            if constexpr (NV > 0) {
+                double cv[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) cv[k] = ci[k];
+#pragma unroll 1
+                for (int k = 0; k < NV; ++k) {
+                    double gk = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NV; ++l) gk += G[k * NV + l] * cv[l];
+                    z += ci[k] * gk;                 // ci[k] == cv[k], read from memory (k not unrolled)
+                }
+            } else {
+                for (int k = 0; k < nv; ++k) {
+                    double gk = 0.0;
+                    for (int l = 0; l < nv; ++l) gk += G[k * nv + l] * ci[l];
+                    z += ci[k] * gk;
+                }
+            }
+        }
         // residual partials of the pairwise work items: strided per thread, then a fixed tree
         gptr<const double> part = glob((const double*)Dp->part);
         const int nslab = Dp->nslab;
-        double mx = 0.0, s1 = 0.0, z = 0.0;
+        double mx = 0.0, s1 = 0.0;
         for (int k = threadIdx.x; k < nslab; k += blockDim.x) {
             mx = fmax(mx, part[(size_t)k * 4 + 0]);
             s1 += part[(size_t)k * 4 + 1];
@@ -1109,7 +1166,7 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         block_reduce3<double, 256>(mx, s1, z, red);
         if (threadIdx.x != 0) return;
         gptr<double> hist = glob(Dp->hist);
-        const double s2 = glob((const double*)Dp->misc)[0];
+        const double s2 = z;
         const int itn = ctrl[0];
         const double rmax = sqrt(mx);
         {
@@ -1267,21 +1324,31 @@ static hipError_t launch_pw_mode(const WorkItem* items, int nitems, const Proble
     return launch_pw<S, NV, kModeSetState, true>(items, nitems, probs, threads, lds, st);
 }
 
-template <int MODE, bool OBS>
+template <int NV, int MODE, bool OBS>
 static hipError_t launch_fx(const WorkItem* items, int nitems, const ProblemDesc<float>* probs, int threads,
                             size_t lds, hipStream_t st) {
     switch (threads) {
         case 256:
-            pairwise_fx_kernel<256, MODE, OBS><<<nitems, 256, lds, st>>>(items, probs);
+            pairwise_fx_kernel<256, NV, MODE, OBS><<<nitems, 256, lds, st>>>(items, probs);
             break;
         case 512:
-            pairwise_fx_kernel<512, MODE, OBS><<<nitems, 512, lds, st>>>(items, probs);
+            pairwise_fx_kernel<512, NV, MODE, OBS><<<nitems, 512, lds, st>>>(items, probs);
             break;
         default:
-            pairwise_fx_kernel<1024, MODE, OBS><<<nitems, 1024, lds, st>>>(items, probs);
+            pairwise_fx_kernel<1024, NV, MODE, OBS><<<nitems, 1024, lds, st>>>(items, probs);
             break;
     }
     return hipGetLastError();
+}
+
+template <int NV>
+static hipError_t launch_fx_mode(const WorkItem* items, int nitems, const ProblemDesc<float>* probs, int mode, bool obs,
+                                 int threads, size_t lds, hipStream_t st) {
+    if (mode == kModeIter)
+        return obs ? launch_fx<NV, kModeIter, true>(items, nitems, probs, threads, lds, st)
+                   : launch_fx<NV, kModeIter, false>(items, nitems, probs, threads, lds, st);
+    if (mode == kModeInit) return launch_fx<NV, kModeInit, true>(items, nitems, probs, threads, lds, st);
+    return launch_fx<NV, kModeSetState, true>(items, nitems, probs, threads, lds, st);
 }
 
 // nv: the (common) number of basis coefficients of the launch's problems, or 0 if they differ.
@@ -1291,12 +1358,8 @@ hipError_t launch_pairwise(const WorkItem* items, int nitems, const ProblemDesc<
                            int threads, size_t lds, int nv, bool obs, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     if constexpr (std::is_same<S, float>::value) {
-        (void)nv;
-        if (mode == kModeIter)
-            return obs ? launch_fx<kModeIter, true>(items, nitems, probs, threads, lds, st)
-                       : launch_fx<kModeIter, false>(items, nitems, probs, threads, lds, st);
-        if (mode == kModeInit) return launch_fx<kModeInit, true>(items, nitems, probs, threads, lds, st);
-        return launch_fx<kModeSetState, true>(items, nitems, probs, threads, lds, st);
+        if (nv == 11) return launch_fx_mode<11>(items, nitems, probs, mode, obs, threads, lds, st);
+        return launch_fx_mode<0>(items, nitems, probs, mode, obs, threads, lds, st);
     } else {
         if (nv == 11) return launch_pw_mode<S, 11>(items, nitems, probs, mode, obs, threads, lds, st);
         return launch_pw_mode<S, 0>(items, nitems, probs, mode, obs, threads, lds, st);
@@ -1326,16 +1389,23 @@ static hipError_t set_lds_nv(size_t lds) {
     return set_lds_one<S, NV, kModeSetState, true>(lds);
 }
 
-template <int MODE, bool OBS>
-static hipError_t set_lds_fx(size_t lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<256, MODE, OBS>,
+template <int NV, int MODE, bool OBS>
+static hipError_t set_lds_fx1(size_t lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<256, NV, MODE, OBS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<512, MODE, OBS>,
+    e = hipFuncSetAttribute((const void*)pairwise_fx_kernel<512, NV, MODE, OBS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)pairwise_fx_kernel<1024, MODE, OBS>,
+    return hipFuncSetAttribute((const void*)pairwise_fx_kernel<1024, NV, MODE, OBS>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int MODE, bool OBS>
+static hipError_t set_lds_fx(size_t lds) {
+    hipError_t e = set_lds_fx1<11, MODE, OBS>(lds);
+    if (e != hipSuccess) return e;
+    return set_lds_fx1<0, MODE, OBS>(lds);
 }
 
 template <typename S>
