@@ -112,7 +112,7 @@ struct ProblemDesc {
     S* lam;                     // [T][3][np] multipliers
     S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
     S* X;                       // [T][3][n]  positions P c of the current coefficients
-    double* misc;               // [4]        reserved
+    unsigned* lflag;            // [T][ceil(np/64)] FP32: 0 when the 64-row group's multipliers are all +0
     double* c;                  // [3][ldc]   coefficients (agent-major per axis)
     double* ceq;                // [3][ldc]   c_eq = K12^{-1} b_eq (boundary part of the product)
     double* q;                  // [3][ldq]   [rho A_fc^T b_fc ; b_eq]  (eq. kkt_step_x)

@@ -94,7 +94,7 @@ struct Engine {
         int n = 0, np = 0, T = 0, nv = 0, ldq = 0, ldc = 0;
         int n_obs = 0;                       // static obstacles (np counts their rows)
         size_t o_obs = 0;
-        size_t o_lam = 0, o_ssum = 0, o_X = 0, o_misc = 0, o_c = 0, o_ceq = 0, o_q = 0, o_r = 0, o_qf = 0,
+        size_t o_lam = 0, o_ssum = 0, o_X = 0, o_lflag = 0, o_c = 0, o_ceq = 0, o_q = 0, o_r = 0, o_qf = 0,
                o_rf = 0, o_part = 0, o_hist = 0, bytes = 0;
         char* base = nullptr;        // device block of this slot
         size_t block = 0;            // bytes of that block (own blocks only)
@@ -281,7 +281,7 @@ struct Engine {
         P.o_lam = off;  off += al(sizeof(S) * (size_t)P.T * 3 * P.np);
         P.o_ssum = off; off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
         P.o_X = off;    off += al(sizeof(S) * (size_t)P.T * 3 * P.n);
-        P.o_misc = off; off += al(sizeof(double) * 4);
+        P.o_lflag = off; off += al(sizeof(unsigned) * (size_t)P.T * ((P.np + 63) / 64));
         P.o_c = off;    off += al(sizeof(double) * 3 * (size_t)P.ldc);
         P.o_ceq = off;  off += al(sizeof(double) * 3 * (size_t)P.ldc);
         P.o_q = off;    off += al(sizeof(double) * 3 * (size_t)P.ldq);
@@ -367,7 +367,7 @@ struct Engine {
         D.lam = (S*)(b + P.o_lam);
         D.ssum = (S*)(b + P.o_ssum);
         D.X = (S*)(b + P.o_X);
-        D.misc = (double*)(b + P.o_misc);
+        D.lflag = (unsigned*)(b + P.o_lflag);
         D.c = (double*)(b + P.o_c);
         D.ceq = (double*)(b + P.o_ceq);
         D.q = (double*)(b + P.o_q);
@@ -423,11 +423,13 @@ struct Engine {
     }
 
     // LDS of the pairwise kernel per instant of a work item.  FP32: positions (x, y, z, 0),
-    // 16 n bytes, and the fixed-point corrections of the per-agent sums, 24 n bytes, an area
-    // that first holds the basis row (8 n_v bytes).  FP64: the FP64 sum over agents of X,
+    // 16 n bytes, the fixed-point corrections of the per-agent sums, 24 n bytes, an area
+    // that first holds the basis row (8 n_v bytes), and the multiplier group flags, 4 bytes
+    // per 64 rows.  FP64: the FP64 sum over agents of X,
     // positions X and b_fc (or its corrections) and two flag words per 32 pairs.
     static size_t pairwise_lds_per_instant(const Prob& P) {
-        if (std::is_same<S, float>::value) return (size_t)16 * P.n + std::max((size_t)24 * P.n, (size_t)8 * P.nv);
+        if (std::is_same<S, float>::value)
+            return (size_t)16 * P.n + std::max((size_t)24 * P.n, (size_t)8 * P.nv) + (size_t)4 * ((P.np + 63) / 64);
         return (size_t)3 * sizeof(double) + (size_t)3 * (P.n + P.np) * sizeof(S) +
                (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
     }

@@ -594,7 +594,9 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
     const int nv = NV > 0 ? NV : Dp->nv;
     long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n], first [tc][nv] doubles
-    S* Os = reinterpret_cast<S*>(Acc + (size_t)tc * max(3 * n, nv));     // [n_obs][kObs]
+    const int ngr = (np + 63) >> 6;                                      // 64-row multiplier groups
+    unsigned* Fs = reinterpret_cast<unsigned*>(Acc + (size_t)tc * max(3 * n, nv));   // [tc][ngr] group flags
+    S* Os = reinterpret_cast<S*>(Fs + (size_t)tc * ngr);                 // [n_obs][kObs]
     __shared__ int any_general;                    // some row took the general branch (iteration)
     const int tid = threadIdx.x;
 
@@ -615,12 +617,23 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     };
     const int axis_bytes = np * (int)sizeof(S);
     const unsigned lane_bytes = (unsigned)pl * sizeof(S);
+    // The rows of a wavefront for one u are 64 consecutive rows from a multiple of 64: one
+    // multiplier group, whose flag (0: every multiplier of the group is +0 on every axis)
+    // decides whether its multipliers are read.  A group read as 0 takes out-of-range buffer
+    // offsets, which return +0 without a memory access.
+    const int wrow = __builtin_amdgcn_readfirstlane(pl & ~63);
+    gptr<unsigned> lflag = glob(Dp->lflag);
 
-    unsigned code[U];
+    unsigned code[U], Fl[U] = {0u, 0u, 0u, 0u};
     S L[U][3], Q[U][3];
     auto fetch = [&](int kc, int ki, size_t first) {
         const int pb = kc * cstride;
         const __amdgpu_buffer_rsrc_t rs = rsrc_at(first, kc);
+        if (MODE == kModeIter) {
+            const unsigned* fr = Fs + (size_t)(tgid + ki * tg) * ngr;
+#pragma unroll
+            for (int u = 0; u < U; ++u) Fl[u] = fr[min((pb + u * pw + wrow) >> 6, ngr - 1)];
+        }
         if (ki == 0) {
 #pragma unroll
             for (int u = 0; u < U; ++u) code[u] = pairs[min(pb + u * pw + pl, np - 1)];   // past np: unused
@@ -630,7 +643,8 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             const int p = pb + u * pw + pl;
             const bool ok = p < np;
             if (MODE != kModeInit) {
-                const unsigned vo = ok ? lane_bytes : kOutOfRange;   // past the last row: 0
+                // past the last row, or a group flagged all +0: 0
+                const unsigned vo = (ok && (MODE != kModeIter || Fl[u] != 0)) ? lane_bytes : kOutOfRange;
                 const int so = u * pw * (int)sizeof(S);
                 L[u][0] = Buf<S>::load(rs, vo, so);
                 L[u][1] = Buf<S>::load(rs, vo, so + axis_bytes);
@@ -649,8 +663,6 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             }
         }
     };
-    if (nit > 0) fetch(0, 0, first0);
-
     if (n_obs > 0) {
         gptr<const S> og = glob(Dp->obs);
         for (int idx = tid; idx < n_obs * kObs; idx += BLOCK) Os[idx] = og[idx];
@@ -667,7 +679,10 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         const int ldc = Dp->ldc;
         double* Pl = reinterpret_cast<double*>(Acc);                    // [tc][nv]
         for (int idx = tid; idx < tc * nv; idx += BLOCK) Pl[idx] = Pm[(size_t)t0 * nv + idx];
+        if (MODE == kModeIter)
+            for (int idx = tid; idx < tc * ngr; idx += BLOCK) Fs[idx] = lflag[(size_t)t0 * ngr + idx];
         __syncthreads();
+        if (nit > 0) fetch(0, 0, first0);
         float* Xf = reinterpret_cast<float*>(Xs);
         const int n3 = 3 * n;
         const int G = max(1, BLOCK / n3);
@@ -712,11 +727,14 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     int kc = 0, ki = 0;
     size_t f_cur = first0, c_first = first0;
     for (int k = 0; k < nit; ++k) {
-        unsigned cc[U];
+        unsigned cc[U], Flc[U];
+        bool nzl[U];                                   // the row's multiplier after this pass is not +0
         S Lc[U][3], Qc[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             cc[u] = code[u];
+            Flc[u] = Fl[u];
+            nzl[u] = false;
             Lc[u][0] = L[u][0]; Lc[u][1] = L[u][1]; Lc[u][2] = L[u][2];
             if (MODE == kModeSetState) { Qc[u][0] = Q[u][0]; Qc[u][1] = Q[u][1]; Qc[u][2] = Q[u][2]; }
         }
@@ -779,6 +797,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             };
             if (MODE == kModeSetState) {
                 record(Qc[u][0] - lx * irho - dx, Qc[u][1] - ly * irho - dy, Qc[u][2] - lzm * irho - dz);
+                nzl[u] = (bits_of(lx) | bits_of(ly) | bits_of(lzm)) != 0;
                 continue;
             }
             const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
@@ -833,6 +852,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                 rmax = fmax(rmax, fn2);
                 rsum += fn2;
                 general = true;
+                nzl[u] = (bits_of(nlx) | bits_of(nly) | bits_of(nlz)) != 0;
             }
             // an iteration stores only the multipliers whose bits change
             const int so = u * pw * (int)sizeof(S);
@@ -851,6 +871,14 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                 }
                 if (dbg_d_p) glob(dbg_d_p)[(size_t)(t0 + tl) * np + p] = dd;
             }
+        }
+        // group flags after this pass: stored where they change (every group outside iterations)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = (pb + u * pw + wrow) >> 6;
+            const unsigned any = __ballot(nzl[u]) != 0ull ? 1u : 0u;
+            if (g < ngr && (tid & 63) == 0 && (MODE != kModeIter || any != (Flc[u] != 0 ? 1u : 0u)))
+                lflag[(size_t)(t0 + tl) * ngr + g] = any;
         }
     }
     if (MODE == kModeIter && general) any_general = 1;
