@@ -406,7 +406,7 @@ struct Engine {
         Prob& P = probs[q];
         const int cap = device_lds_limit() - 1024;   // room for the kernel's static reduction buffer
         const size_t per_t = pairwise_lds_per_instant(P);
-        const size_t fixed = (size_t)kObs * P.n_obs * sizeof(S);
+        const size_t fixed = pairwise_lds_fixed(P);
         int tc = std::max(1, items_per_wg / std::max(1, P.np));
         tc = std::min(tc, P.T);
         while (tc > 1 && per_t * tc + fixed > (size_t)cap) --tc;
@@ -424,18 +424,27 @@ struct Engine {
 
     // LDS of the pairwise kernel per instant of a work item.  FP32: positions (x, y, z, 0),
     // 16 n bytes, the fixed-point corrections of the per-agent sums, 24 n bytes, an area
-    // that first holds the basis row (8 n_v bytes), and the multiplier group flags, 4 bytes
-    // per 64 rows.  FP64: the FP64 sum over agents of X,
+    // that first holds the basis row (8 n_v bytes), and the multiplier group flags before
+    // and after the pass, 8 bytes per 64 rows.  FP64: the FP64 sum over agents of X,
     // positions X and b_fc (or its corrections) and two flag words per 32 pairs.
     static size_t pairwise_lds_per_instant(const Prob& P) {
         if (std::is_same<S, float>::value)
-            return (size_t)16 * P.n + std::max((size_t)24 * P.n, (size_t)8 * P.nv) + (size_t)4 * ((P.np + 63) / 64);
+            return (size_t)16 * P.n + std::max((size_t)24 * P.n, (size_t)8 * P.nv) + (size_t)8 * ((P.np + 63) / 64);
         return (size_t)3 * sizeof(double) + (size_t)3 * (P.n + P.np) * sizeof(S) +
                (size_t)2 * ((P.np + 31) / 32) * sizeof(unsigned);
     }
 
+    // LDS of the pairwise kernel per work item besides the instants: the obstacle table;
+    // FP32 also the agents' bounding boxes (24 n bytes) and, per 64 rows, the kept-row bits
+    // and the group's flag over the item (12 bytes).
+    static size_t pairwise_lds_fixed(const Prob& P) {
+        size_t f = (size_t)kObs * P.n_obs * sizeof(S);
+        if (std::is_same<S, float>::value) f += (size_t)24 * P.n + (size_t)12 * ((P.np + 63) / 64);
+        return f;
+    }
+
     static mato_status check_lds(const Prob& P) {
-        const size_t per_t = pairwise_lds_per_instant(P) + (size_t)kObs * P.n_obs * sizeof(S);
+        const size_t per_t = pairwise_lds_per_instant(P) + pairwise_lds_fixed(P);
         if (per_t > (size_t)(device_lds_limit() - 1024)) {
             set_error("n = %d, n_obs = %d needs %zu bytes of LDS per instant, device allows %d", P.n, P.n_obs,
                       per_t, device_lds_limit() - 1024);

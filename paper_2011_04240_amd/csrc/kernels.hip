@@ -563,6 +563,34 @@ __device__ inline long long fx_of(float v) {
     return (long long)u;
 }
 
+// The plain projection of eqs. (sphere_project), (step_d) for one pair-instant past the
+// far-pair shortcut, trig-free (see the top of this file): d e = (px, py, pz) and d, from
+// delta, s^2 = q2 and the multiplier.  One definition for both row orders of the FP32
+// kernel, so that they agree bit for bit.
+__device__ inline void project_plain(float dx, float dy, float dz, float q2, float lx, float ly, float lzm,
+                                     float irho, float lzp, float& px, float& py, float& pz, float& dd) {
+    if (q2 > 0) {
+        const float D2 = dx * dx + dy * dy + dz * dz;
+        const float rs_ = Recip<float>::rsq(q2);                        // 1 / s
+        const float dl = dx * lx + dy * ly + dz * lzm;
+        const float w = fmax(rs_, 1.f + dl * irho * Recip<float>::rcp(D2));
+        px = w * dx;
+        py = w * dy;
+        pz = w * dz;
+        dd = w * (q2 * rs_);                                            // d = w s
+    } else {                                                            // delta = 0: e = (0, 0, l_z)
+        dd = fmax(1.f, lzm * irho / lzp);
+        px = 0;
+        py = 0;
+        pz = dd * lzp;
+    }
+}
+
+// s^2 of a pair at least this far apart (from bounding boxes) at every instant of a work
+// item is above the shortcut's 1.0001 at each of them: the margin covers the rounding of
+// the two evaluations of the same expression.
+constexpr float kBroadClear = 1.0002f;
+
 template <int BLOCK, int NV, int MODE, bool OBS>
 __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __restrict__ items,
                                                             const ProblemDesc<float>* __restrict__ probs) {
@@ -591,14 +619,20 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     const S irho_b = (MODE == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->sirho_next : irho;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
     const int nv = NV > 0 ? NV : Dp->nv;
-    long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n], first [tc][nv] doubles
     const int ngr = (np + 63) >> 6;                                      // 64-row multiplier groups
-    unsigned* Fs = reinterpret_cast<unsigned*>(Acc + (size_t)tc * max(3 * n, nv));   // [tc][ngr] group flags
-    S* Os = reinterpret_cast<S*>(Fs + (size_t)tc * ngr);                 // [n_obs][kObs]
+    float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
+    long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n], first [tc][nv] doubles
+    unsigned long long* Fb = reinterpret_cast<unsigned long long*>(Acc + (size_t)tc * max(3 * n, nv));  // [ngr]
+    unsigned* Fs = reinterpret_cast<unsigned*>(Fb + ngr);               // [tc][ngr] group flags
+    unsigned* NFs = Fs + (size_t)tc * ngr;                               // [tc][ngr] flags after the pass
+    unsigned* Gf = NFs + (size_t)tc * ngr;                               // [ngr] some instant flagged
+    S* Os = reinterpret_cast<S*>(Gf + ngr);                              // [n_obs][kObs]
+    S* Bs = Os + (size_t)n_obs * kObs;                                   // [n][6] boxes over the item
     __shared__ int any_general;                    // some row took the general branch (iteration)
+    __shared__ int wcnt[BLOCK / 64];
     const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
 
     int pw = 64;
     while (pw < np && pw < BLOCK) pw <<= 1;
@@ -719,14 +753,82 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         __syncthreads();                                               // Pl is read before Acc is zeroed
         for (int idx = tid; idx < tc * 3 * n; idx += BLOCK) Acc[idx] = 0;
         if (tid == 0) any_general = 0;
+        if (MODE == kModeIter) {
+            for (int idx = tid; idx < tc * ngr; idx += BLOCK) NFs[idx] = 0u;
+            for (int g = tid; g < ngr; g += BLOCK) {
+                unsigned f = 0u;
+                for (int tl = 0; tl < tc; ++tl) f |= Fs[tl * ngr + g];
+                Gf[g] = f;
+            }
+            // every agent's bounding box over the item's instants (unbounded if a position is NaN)
+            for (int col = tid; col < n3; col += BLOCK) {
+                const int a = col / n, i = col - a * n;
+                float lo = Xf[(size_t)i * 4 + a], hi = lo;
+                bool bad = lo != lo;
+                for (int tl = 1; tl < tc; ++tl) {
+                    const float x = Xf[((size_t)tl * n + i) * 4 + a];
+                    lo = fminf(lo, x);
+                    hi = fmaxf(hi, x);
+                    bad |= x != x;
+                }
+                Bs[i * 6 + 2 * a] = bad ? -INFINITY : lo;
+                Bs[i * 6 + 2 * a + 1] = bad ? INFINITY : hi;
+            }
+        }
     }
     __syncthreads();
+
+    // Broad phase (iterations with the plain projection and no parity outputs): a row whose
+    // group has no multiplier flagged at any instant of the item and whose agents' boxes keep
+    // s^2 above kBroadClear takes the far-pair shortcut at every instant, so nothing is done
+    // for it.  The other rows' bits (Fb) are kept; when they are at most half the rows, only
+    // they are worked through, instant by instant (the row list), else every row is, in the
+    // streaming order below.
+    bool use_list = false;
+    if (MODE == kModeIter && !shifted && !dbg_on) {
+        constexpr int nw = BLOCK / 64;
+        int cntw = 0;
+        for (int g = wv; g < ngr; g += nw) {
+            const int p = (g << 6) + lane;
+            bool fail = false;
+            if (p < np) {
+                const unsigned cd = pairs[p];
+                const int i = (int)(cd & 0xffffu), j = (int)(cd >> 16);
+                const S* bi = Bs + i * 6;
+                S gx, gy, gz, ia2p = ia2, ib2p = ib2;
+                if (!OBS || j < n) {
+                    const S* bj = Bs + j * 6;
+                    gx = fmaxf(0.f, fmaxf(bi[0] - bj[1], bj[0] - bi[1]));
+                    gy = fmaxf(0.f, fmaxf(bi[2] - bj[3], bj[2] - bi[3]));
+                    gz = fmaxf(0.f, fmaxf(bi[4] - bj[5], bj[4] - bi[5]));
+                } else {
+                    const S* ob = Os + (j - n) * kObs;
+                    gx = fmaxf(0.f, fmaxf(bi[0] - ob[0], ob[0] - bi[1]));
+                    gy = fmaxf(0.f, fmaxf(bi[2] - ob[1], ob[1] - bi[3]));
+                    gz = fmaxf(0.f, fmaxf(bi[4] - ob[2], ob[2] - bi[5]));
+                    ia2p = ob[3];
+                    ib2p = ob[4];
+                }
+                const S q2g = (gx * gx + gy * gy) * ia2p + gz * gz * ib2p;
+                fail = !(q2g > kBroadClear) || Gf[g] != 0u;
+            }
+            const unsigned long long b = __ballot(fail);
+            if (lane == 0) Fb[g] = b;
+            cntw += __popcll(b);
+        }
+        if (lane == 0) wcnt[wv] = cntw;
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += wcnt[w];
+        use_list = 2 * tot <= np;
+    }
 
     S rmax = 0, rsum = 0;
     bool general = false;
     int kc = 0, ki = 0;
     size_t f_cur = first0, c_first = first0;
-    for (int k = 0; k < nit; ++k) {
+    const int nit_stream = use_list ? 0 : nit;
+    for (int k = 0; k < nit_stream; ++k) {
         unsigned cc[U], Flc[U];
         bool nzl[U];                                   // the row's multiplier after this pass is not +0
         S Lc[U][3], Qc[U][3];
@@ -809,21 +911,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             if (fast) continue;
             S px, py, pz, dd;
             if (!shifted) {
-                if (q2 > 0) {
-                    const S D2 = dx * dx + dy * dy + dz * dz;
-                    const S rs_ = Recip<S>::rsq(q2);                    // 1 / s
-                    const S dl = dx * lx + dy * ly + dz * lzm;
-                    const S w = fmax(rs_, S(1) + dl * irho * Recip<S>::rcp(D2));
-                    px = w * dx;
-                    py = w * dy;
-                    pz = w * dz;
-                    dd = w * (q2 * rs_);                                // d = w s
-                } else {                                                // delta = 0: e = (0, 0, l_z)
-                    dd = fmax(S(1), lzm * irho / lzp);
-                    px = 0;
-                    py = 0;
-                    pz = dd * lzp;
-                }
+                project_plain(dx, dy, dz, q2, lx, ly, lzm, irho, lzp, px, py, pz, dd);
             } else {
                 // variant: project v = delta + lambda/rho; then d = max(1, s_v), d e = max(1/s_v, 1) v
                 const S vx = dx + lx * irho, vy = dy + ly * irho, vz = dz + lzm * irho;
@@ -881,13 +969,97 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                 lflag[(size_t)(t0 + tl) * ngr + g] = any;
         }
     }
+    if (MODE == kModeIter && use_list) {
+        // The row list: a wavefront takes its groups' kept rows; lane l < m of the compacted
+        // group holds its l-th kept row (a permutation across the lanes), and the m rows times
+        // tc instants are spread over the 64 lanes, 64 / m instants per pass.
+        constexpr int nw = BLOCK / 64;
+        for (int g = wv; g < ngr; g += nw) {
+            const unsigned long long mask = Fb[g];
+            if (mask == 0ull) continue;                                 // uniform
+            const int m = __popcll(mask);
+            const bool kept = ((mask >> lane) & 1ull) != 0ull;
+            const int below = __popcll(mask & ((1ull << lane) - 1ull));
+            const int dst = kept ? below : m + (lane - below);
+            const int rowc = __builtin_amdgcn_ds_permute(dst << 2, (g << 6) + lane);
+            const int q = 64 / m;
+            const int tq = lane / m, l = lane - tq * m;
+            const int p = __builtin_amdgcn_ds_bpermute(l << 2, rowc);   // < np: a kept row
+            if (tq >= q) continue;
+            const unsigned cd = pairs[p];
+            const int i = (int)(cd & 0xffffu), j = (int)(cd >> 16);
+            S ia2p = ia2, ib2p = ib2, lzp = lzl;
+            const S* ob = nullptr;
+            if (OBS && j >= n) {
+                ob = Os + (j - n) * kObs;
+                ia2p = ob[3];
+                ib2p = ob[4];
+                lzp = ob[5];
+            }
+            for (int tl = tq; tl < tc; tl += q) {
+                const float4 xi = Xs[(size_t)tl * n + i];
+                S xj, yj, zj;
+                if (!OBS || j < n) {
+                    const float4 xv = Xs[(size_t)tl * n + j];
+                    xj = xv.x;
+                    yj = xv.y;
+                    zj = xv.z;
+                } else {
+                    xj = ob[0];
+                    yj = ob[1];
+                    zj = ob[2];
+                }
+                const S dx = xi.x - xj;
+                const S dy = xi.y - yj;
+                const S dz = xi.z - zj;
+                const size_t e = (size_t)(t0 + tl) * 3 * np + p;
+                S lx = 0, ly = 0, lzm = 0;
+                if (Fs[tl * ngr + g] != 0u) {
+                    lx = lam[e];
+                    ly = lam[e + np];
+                    lzm = lam[e + 2 * (size_t)np];
+                }
+                const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+                if ((q2 > S(1.0001)) & ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0)) continue;
+                S px, py, pz, dd;
+                project_plain(dx, dy, dz, q2, lx, ly, lzm, irho, lzp, px, py, pz, dd);
+                const S fx_ = dx - px, fy_ = dy - py, fz_ = dz - pz;
+                const S nlx = lx + rho * fx_;
+                const S nly = ly + rho * fy_;
+                const S nlz = lzm + rho * fz_;
+                const S fn2 = fx_ * fx_ + fy_ * fy_ + fz_ * fz_;
+                rmax = fmax(rmax, fn2);
+                rsum += fn2;
+                general = true;
+                if (bits_of(nlx) != bits_of(lx)) lam[e] = nlx;
+                if (bits_of(nly) != bits_of(ly)) lam[e + np] = nly;
+                if (bits_of(nlz) != bits_of(lzm)) lam[e + 2 * (size_t)np] = nlz;
+                if ((bits_of(nlx) | bits_of(nly) | bits_of(nlz)) != 0) atomicOr(&NFs[tl * ngr + g], 1u);
+                const S cx = px - nlx * irho_b - dx, cy = py - nly * irho_b - dy, cz = pz - nlz * irho_b - dz;
+                if ((bits_of(cx) | bits_of(cy) | bits_of(cz)) != 0) {
+                    long long* A = Acc + (size_t)tl * 3 * n;
+                    const long long fx = fx_of(cx), fy = fx_of(cy), fz = fx_of(cz);
+                    atomicAdd((unsigned long long*)&A[i], (unsigned long long)fx);
+                    atomicAdd((unsigned long long*)&A[n + i], (unsigned long long)fy);
+                    atomicAdd((unsigned long long*)&A[2 * n + i], (unsigned long long)fz);
+                    if (!OBS || j < n) {
+                        atomicAdd((unsigned long long*)&A[j], (unsigned long long)(-fx));
+                        atomicAdd((unsigned long long*)&A[n + j], (unsigned long long)(-fy));
+                        atomicAdd((unsigned long long*)&A[2 * n + j], (unsigned long long)(-fz));
+                    }
+                }
+            }
+        }
+    }
     if (MODE == kModeIter && general) any_general = 1;
     __syncthreads();
+    if (MODE == kModeIter && use_list)                   // the row list's group flags where they change
+        for (int idx = tid; idx < tc * ngr; idx += BLOCK)
+            if (NFs[idx] != Fs[idx]) lflag[(size_t)t0 * ngr + idx] = NFs[idx];
 
     // S_i = (n + n_obs) X_i - sum_j X_j + corrections, per (instant, axis) row by one
     // wavefront: the agent sum as an exact int64 butterfly, every lane with the same value
     const int nn = n + n_obs;
-    const int wv = tid >> 6, lane = tid & 63;
     for (int r = wv; r < tc * 3; r += BLOCK / 64) {
         const int tl = r / 3, a = r - tl * 3;
         const float* Xr = reinterpret_cast<const float*>(Xs + (size_t)tl * n) + a;   // stride 4
