@@ -110,7 +110,7 @@ struct ProblemDesc {
     const S* obs;               // [n_obs][kObs] obstacle table
     const double* smat;         // structured solve operands of the plan (nullptr: dense inverse)
     S* lam;                     // [T][3][np] multipliers
-    S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T)
+    S* ssum;                    // [T][3][n]  per-agent sums of b_fc (A_fc^T b before P^T); FP32: their corrections C
     S* X;                       // [T][3][n]  positions P c of the current coefficients
     unsigned* lflag;            // [T][ceil(np/64)] FP32: 0 when the 64-row group's multipliers are all +0
     double* c;                  // [3][ldc]   coefficients (agent-major per axis)

@@ -406,7 +406,7 @@ struct Engine {
         Prob& P = probs[q];
         const int cap = device_lds_limit() - 1024;   // room for the kernel's static reduction buffer
         const size_t per_t = pairwise_lds_per_instant(P);
-        const size_t fixed = pairwise_lds_fixed(P);
+        const size_t fixed = pairwise_lds_fixed(P, threads);
         int tc = std::max(1, items_per_wg / std::max(1, P.np));
         tc = std::min(tc, P.T);
         while (tc > 1 && per_t * tc + fixed > (size_t)cap) --tc;
@@ -435,16 +435,17 @@ struct Engine {
     }
 
     // LDS of the pairwise kernel per work item besides the instants: the obstacle table;
-    // FP32 also the agents' bounding boxes (24 n bytes) and, per 64 rows, the kept-row bits
-    // and the group's flag over the item (12 bytes).
-    static size_t pairwise_lds_fixed(const Prob& P) {
+    // FP32 also the agents' bounding boxes (24 n bytes), per 64 rows the kept-row bits and
+    // the group's flag over the item (12 bytes), and a 64-row list per wavefront (512 bytes).
+    static size_t pairwise_lds_fixed(const Prob& P, int nthreads) {
         size_t f = (size_t)kObs * P.n_obs * sizeof(S);
-        if (std::is_same<S, float>::value) f += (size_t)24 * P.n + (size_t)12 * ((P.np + 63) / 64);
+        if (std::is_same<S, float>::value)
+            f += (size_t)24 * P.n + (size_t)12 * ((P.np + 63) / 64) + (size_t)512 * (nthreads / 64);
         return f;
     }
 
     static mato_status check_lds(const Prob& P) {
-        const size_t per_t = pairwise_lds_per_instant(P) + pairwise_lds_fixed(P);
+        const size_t per_t = pairwise_lds_per_instant(P) + pairwise_lds_fixed(P, 1024);
         if (per_t > (size_t)(device_lds_limit() - 1024)) {
             set_error("n = %d, n_obs = %d needs %zu bytes of LDS per instant, device allows %d", P.n, P.n_obs,
                       per_t, device_lds_limit() - 1024);

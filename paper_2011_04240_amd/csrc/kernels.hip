@@ -534,11 +534,13 @@ __global__ __launch_bounds__(BLOCK) void pairwise_kernel(const WorkItem* __restr
 //
 // S_i(t) = sum_{j>i} b_ij - sum_{j<i} b_ji + sum_o (x_o + b_io).  With every b written as
 // delta + corr (delta = X_i - X_j, or X_i - x_o on an obstacle row; corr = b - delta):
-//     S_i = (n + n_obs) X_i - sum_j X_j + sum over the rows of agent i of (+-corr),
-// + where i is the row's first member, - where it is the second.  The positions and the
-// corrections enter in fixed point with kFx fractional bits (int64): those sums are exact,
-// so the rows' corrections can be added with LDS atomics in whatever order the lanes reach
-// them and S_i does not depend on the tile shape or the batch.  S_i is rounded to FP32
+//     S_i = (n + n_obs) X_i - sum_j X_j + C_i,  C_i = sum over the rows of agent i of (+-corr),
+// + where i is the row's first member, - where it is the second.  This kernel forms C_i; the
+// positions' part enters the linear term as P^T of it, (n + n_obs) P^T P c_i -
+// P^T P sum_j c_j, in FP64 from the coefficients (no rounding of the positions).  The
+// corrections enter C_i in fixed point with kFx fractional bits (int64): those sums are
+// exact, so the rows' corrections can be added with LDS atomics in whatever order the lanes
+// reach them and C_i does not depend on the tile shape or the batch.  C_i is rounded to FP32
 // once.  A row whose corr is +0 on every axis (b = delta: the usual case away from
 // collisions) adds nothing.  The rows come in the plan's tournament order, so the lanes
 // of a wavefront touch different agents and the atomics rarely collide.
@@ -563,27 +565,54 @@ __device__ inline long long fx_of(float v) {
     return (long long)u;
 }
 
+// Per-pair-instant arithmetic of the FP32 kernel.  Every rounding step is written out
+// (fused where fmaf says so, nothing else contracted), so that the two row orders of the
+// kernel and its broad phase evaluate the same operations bit for bit wherever they are
+// inlined.
+//
+// s^2 = (dx^2 + dy^2) / l_xy^2 + dz^2 / l_z^2: nondecreasing in |dx|, |dy|, |dz|.
+__device__ inline float scaled_sq(float dx, float dy, float dz, float ia2p, float ib2p) {
+#pragma clang fp contract(off)
+    return fmaf(fmaf(dx, dx, dy * dy), ia2p, (dz * dz) * ib2p);
+}
+
 // The plain projection of eqs. (sphere_project), (step_d) for one pair-instant past the
 // far-pair shortcut, trig-free (see the top of this file): d e = (px, py, pz) and d, from
-// delta, s^2 = q2 and the multiplier.  One definition for both row orders of the FP32
-// kernel, so that they agree bit for bit.
+// delta, s^2 = q2 and the multiplier.
 __device__ inline void project_plain(float dx, float dy, float dz, float q2, float lx, float ly, float lzm,
                                      float irho, float lzp, float& px, float& py, float& pz, float& dd) {
+#pragma clang fp contract(off)
     if (q2 > 0) {
-        const float D2 = dx * dx + dy * dy + dz * dz;
+        const float D2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         const float rs_ = Recip<float>::rsq(q2);                        // 1 / s
-        const float dl = dx * lx + dy * ly + dz * lzm;
-        const float w = fmax(rs_, 1.f + dl * irho * Recip<float>::rcp(D2));
+        const float dl = fmaf(dx, lx, fmaf(dy, ly, dz * lzm));
+        const float w = fmaxf(rs_, fmaf(dl * irho, Recip<float>::rcp(D2), 1.f));
         px = w * dx;
         py = w * dy;
         pz = w * dz;
         dd = w * (q2 * rs_);                                            // d = w s
     } else {                                                            // delta = 0: e = (0, 0, l_z)
-        dd = fmax(1.f, lzm * irho / lzp);
+        dd = fmaxf(1.f, (lzm * irho) / lzp);
         px = 0;
         py = 0;
         pz = dd * lzp;
     }
+}
+
+// The multiplier step of eq. (lag_update) with f_c = delta - d e, the row's |f_c|^2, and
+// b_fc - delta = d e - lambda_new / rho - delta (the row's correction of the agent sums).
+__device__ inline void row_update(float dx, float dy, float dz, float px, float py, float pz, float lx, float ly,
+                                  float lzm, float rho, float& nlx, float& nly, float& nlz, float& fn2) {
+#pragma clang fp contract(off)
+    const float fx = dx - px, fy = dy - py, fz = dz - pz;
+    nlx = fmaf(rho, fx, lx);
+    nly = fmaf(rho, fy, ly);
+    nlz = fmaf(rho, fz, lzm);
+    fn2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
+}
+__device__ inline float row_correction(float p, float nl, float irho_b, float d) {
+#pragma clang fp contract(off)
+    return fmaf(-nl, irho_b, p) - d;
 }
 
 // s^2 of a pair at least this far apart (from bounding boxes) at every instant of a work
@@ -629,6 +658,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     unsigned* Gf = NFs + (size_t)tc * ngr;                               // [ngr] some instant flagged
     S* Os = reinterpret_cast<S*>(Gf + ngr);                              // [n_obs][kObs]
     S* Bs = Os + (size_t)n_obs * kObs;                                   // [n][6] boxes over the item
+    unsigned* Lq = reinterpret_cast<unsigned*>(Bs + (size_t)n * 6);     // [BLOCK/64][64][2] row lists
     __shared__ int any_general;                    // some row took the general branch (iteration)
     __shared__ int wcnt[BLOCK / 64];
     const int tid = threadIdx.x;
@@ -809,7 +839,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                     ia2p = ob[3];
                     ib2p = ob[4];
                 }
-                const S q2g = (gx * gx + gy * gy) * ia2p + gz * gz * ib2p;
+                const S q2g = scaled_sq(gx, gy, gz, ia2p, ib2p);
                 fail = !(q2g > kBroadClear) || Gf[g] != 0u;
             }
             const unsigned long long b = __ballot(fail);
@@ -902,7 +932,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                 nzl[u] = (bits_of(lx) | bits_of(ly) | bits_of(lzm)) != 0;
                 continue;
             }
-            const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+            const S q2 = scaled_sq(dx, dy, dz, ia2p, ib2p);              // s^2 (plain projection)
             // no multiplier (+0) and clear of the collision set by a margin: the general branch
             // gives w = 1, d e = delta, f_c = +0, lambda = +0 (not stored), b_fc = delta (no
             // correction) and a zero residual, bit for bit
@@ -930,13 +960,10 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                     pz = lzp;
                 }
             }
-            const S fx_ = dx - px, fy_ = dy - py, fz_ = dz - pz;
             S nlx = 0, nly = 0, nlz = 0;
             if (MODE == kModeIter) {
-                nlx = lx + rho * fx_;
-                nly = ly + rho * fy_;
-                nlz = lzm + rho * fz_;
-                const S fn2 = fx_ * fx_ + fy_ * fy_ + fz_ * fz_;
+                S fn2;
+                row_update(dx, dy, dz, px, py, pz, lx, ly, lzm, rho, nlx, nly, nlz, fn2);
                 rmax = fmax(rmax, fn2);
                 rsum += fn2;
                 general = true;
@@ -948,7 +975,8 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             if (MODE != kModeIter || bits_of(nly) != bits_of(ly)) Buf<S>::store(nly, rs, lane_bytes, so + axis_bytes);
             if (MODE != kModeIter || bits_of(nlz) != bits_of(lzm))
                 Buf<S>::store(nlz, rs, lane_bytes, so + 2 * axis_bytes);
-            record(px - nlx * irho_b - dx, py - nly * irho_b - dy, pz - nlz * irho_b - dz);
+            record(row_correction(px, nlx, irho_b, dx), row_correction(py, nly, irho_b, dy),
+                   row_correction(pz, nlz, irho_b, dz));
             if (dbg_on) {
                 const size_t e = fc + (size_t)(u * pw + pl);          // (t0 + tl) 3 np + p
                 if (dbg_proj_p) {
@@ -970,72 +998,62 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         }
     }
     if (MODE == kModeIter && use_list) {
-        // The row list: a wavefront takes its groups' kept rows; lane l < m of the compacted
-        // group holds its l-th kept row (a permutation across the lanes), and the m rows times
-        // tc instants are spread over the 64 lanes, 64 / m instants per pass.
+        // The row list: a wavefront collects its groups' kept rows (row, code) in LDS, in
+        // batches of at most 64 rows, and spreads each batch's rows times tc instants over
+        // its lanes (instants padded to a power of two, tcp).
         constexpr int nw = BLOCK / 64;
-        for (int g = wv; g < ngr; g += nw) {
-            const unsigned long long mask = Fb[g];
-            if (mask == 0ull) continue;                                 // uniform
-            const int m = __popcll(mask);
-            const bool kept = ((mask >> lane) & 1ull) != 0ull;
-            const int below = __popcll(mask & ((1ull << lane) - 1ull));
-            const int dst = kept ? below : m + (lane - below);
-            const int rowc = __builtin_amdgcn_ds_permute(dst << 2, (g << 6) + lane);
-            const int q = 64 / m;
-            const int tq = lane / m, l = lane - tq * m;
-            const int p = __builtin_amdgcn_ds_bpermute(l << 2, rowc);   // < np: a kept row
-            if (tq >= q) continue;
-            const unsigned cd = pairs[p];
-            const int i = (int)(cd & 0xffffu), j = (int)(cd >> 16);
-            S ia2p = ia2, ib2p = ib2, lzp = lzl;
-            const S* ob = nullptr;
-            if (OBS && j >= n) {
-                ob = Os + (j - n) * kObs;
-                ia2p = ob[3];
-                ib2p = ob[4];
-                lzp = ob[5];
-            }
-            for (int tl = tq; tl < tc; tl += q) {
+        volatile unsigned* lq = Lq + (size_t)wv * 128;
+        const int lt = tc > 1 ? 32 - __clz(tc - 1) : 0, tcp = 1 << lt;
+        int R = 0;
+        auto run_batch = [&]() {
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < (R << lt); e += 64) {
+                const int r = e >> lt, tl = e & (tcp - 1);
+                if (tl >= tc) continue;
+                const int p = (int)lq[2 * r];
+                const unsigned cd = lq[2 * r + 1];
+                const int g = p >> 6;
+                const int i = (int)(cd & 0xffffu), j = (int)(cd >> 16);
+                S xj, yj, zj, ia2p = ia2, ib2p = ib2, lzp = lzl;
                 const float4 xi = Xs[(size_t)tl * n + i];
-                S xj, yj, zj;
                 if (!OBS || j < n) {
                     const float4 xv = Xs[(size_t)tl * n + j];
                     xj = xv.x;
                     yj = xv.y;
                     zj = xv.z;
                 } else {
+                    const S* ob = Os + (j - n) * kObs;
                     xj = ob[0];
                     yj = ob[1];
                     zj = ob[2];
+                    ia2p = ob[3];
+                    ib2p = ob[4];
+                    lzp = ob[5];
                 }
                 const S dx = xi.x - xj;
                 const S dy = xi.y - yj;
                 const S dz = xi.z - zj;
-                const size_t e = (size_t)(t0 + tl) * 3 * np + p;
+                const size_t el = (size_t)(t0 + tl) * 3 * np + p;
                 S lx = 0, ly = 0, lzm = 0;
                 if (Fs[tl * ngr + g] != 0u) {
-                    lx = lam[e];
-                    ly = lam[e + np];
-                    lzm = lam[e + 2 * (size_t)np];
+                    lx = lam[el];
+                    ly = lam[el + np];
+                    lzm = lam[el + 2 * (size_t)np];
                 }
-                const S q2 = (dx * dx + dy * dy) * ia2p + dz * dz * ib2p;   // s^2 (plain projection)
+                const S q2 = scaled_sq(dx, dy, dz, ia2p, ib2p);          // s^2 (plain projection)
                 if ((q2 > S(1.0001)) & ((bits_of(lx) | bits_of(ly) | bits_of(lzm)) == 0)) continue;
-                S px, py, pz, dd;
+                S px, py, pz, dd, nlx, nly, nlz, fn2;
                 project_plain(dx, dy, dz, q2, lx, ly, lzm, irho, lzp, px, py, pz, dd);
-                const S fx_ = dx - px, fy_ = dy - py, fz_ = dz - pz;
-                const S nlx = lx + rho * fx_;
-                const S nly = ly + rho * fy_;
-                const S nlz = lzm + rho * fz_;
-                const S fn2 = fx_ * fx_ + fy_ * fy_ + fz_ * fz_;
+                row_update(dx, dy, dz, px, py, pz, lx, ly, lzm, rho, nlx, nly, nlz, fn2);
                 rmax = fmax(rmax, fn2);
                 rsum += fn2;
                 general = true;
-                if (bits_of(nlx) != bits_of(lx)) lam[e] = nlx;
-                if (bits_of(nly) != bits_of(ly)) lam[e + np] = nly;
-                if (bits_of(nlz) != bits_of(lzm)) lam[e + 2 * (size_t)np] = nlz;
+                if (bits_of(nlx) != bits_of(lx)) lam[el] = nlx;
+                if (bits_of(nly) != bits_of(ly)) lam[el + np] = nly;
+                if (bits_of(nlz) != bits_of(lzm)) lam[el + 2 * (size_t)np] = nlz;
                 if ((bits_of(nlx) | bits_of(nly) | bits_of(nlz)) != 0) atomicOr(&NFs[tl * ngr + g], 1u);
-                const S cx = px - nlx * irho_b - dx, cy = py - nly * irho_b - dy, cz = pz - nlz * irho_b - dz;
+                const S cx = row_correction(px, nlx, irho_b, dx), cy = row_correction(py, nly, irho_b, dy),
+                        cz = row_correction(pz, nlz, irho_b, dz);
                 if ((bits_of(cx) | bits_of(cy) | bits_of(cz)) != 0) {
                     long long* A = Acc + (size_t)tl * 3 * n;
                     const long long fx = fx_of(cx), fy = fx_of(cy), fz = fx_of(cz);
@@ -1049,7 +1067,23 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
+            R = 0;
+        };
+        for (int g = wv; g < ngr; g += nw) {
+            const unsigned long long mask = Fb[g];
+            if (mask == 0ull) continue;                                 // uniform
+            const int m = __popcll(mask);
+            if (R + m > 64) run_batch();
+            if ((mask >> lane) & 1ull) {
+                const int pos = R + __popcll(mask & ((1ull << lane) - 1ull));
+                const int p = (g << 6) + lane;
+                lq[2 * pos] = (unsigned)p;
+                lq[2 * pos + 1] = pairs[p];
+            }
+            R += m;
         }
+        if (R > 0) run_batch();
     }
     if (MODE == kModeIter && general) any_general = 1;
     __syncthreads();
@@ -1057,21 +1091,12 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         for (int idx = tid; idx < tc * ngr; idx += BLOCK)
             if (NFs[idx] != Fs[idx]) lflag[(size_t)t0 * ngr + idx] = NFs[idx];
 
-    // S_i = (n + n_obs) X_i - sum_j X_j + corrections, per (instant, axis) row by one
-    // wavefront: the agent sum as an exact int64 butterfly, every lane with the same value
-    const int nn = n + n_obs;
-    for (int r = wv; r < tc * 3; r += BLOCK / 64) {
-        const int tl = r / 3, a = r - tl * 3;
-        const float* Xr = reinterpret_cast<const float*>(Xs + (size_t)tl * n) + a;   // stride 4
-        long long sx = 0;
-        for (int j = lane; j < n; j += 64) sx += fx_of(Xr[4 * j]);
-        for (int off = 32; off > 0; off >>= 1) sx += __shfl_xor(sx, off);
-        const long long* Ar = Acc + (size_t)r * n;
-        gptr<S> out = ssum + ((size_t)(t0 + tl) * 3 + a) * n;
-        for (int i = lane; i < n; i += 64) {
-            const long long v = (long long)nn * fx_of(Xr[4 * i]) - sx + Ar[i];
-            out[i] = (S)ldexp((double)v, -kFx);
-        }
+    // The rows' corrections of the agent sums, C_i = S_i - ((n + n_obs) X_i - sum_j X_j), of
+    // the item's instants, rounded once to FP32: the linear-term kernel adds the positions'
+    // part from the coefficients.  [tc][3][n] is one contiguous run of [T][3][n].
+    {
+        gptr<S> out = ssum + (size_t)t0 * 3 * n;
+        for (int idx = tid; idx < tc * 3 * n; idx += BLOCK) out[idx] = (S)ldexp((double)Acc[idx], -kFx);
     }
 
     if (MODE == kModeIter) {
@@ -1226,7 +1251,8 @@ __global__ __launch_bounds__(256) void solve_positions_kernel(const ProblemDesc<
 // One workgroup per problem: g = rho P^T S (FP64) into q[a][0 .. n*nv) (and its FP32
 // copy), then in iteration mode the residual record of this iteration and the
 // convergence test.  A thread owns one (axis, agent) column of S and produces its
-// nv coefficients.
+// nv coefficients.  FP32 problems hold only the corrections C of S: their P^T S_i is
+// P^T C_i + P^T P ((n + n_obs) c_i - sum_j c_j), the second part from the coefficients.
 template <typename S, int NV>
 __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __restrict__ probs, int mode) {
     const ProblemDesc<S>* __restrict__ Dp = probs + blockIdx.x;
@@ -1241,6 +1267,43 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
     gptr<double> q = glob(Dp->q);
     gptr<float> qf = glob(Dp->qf);
     const int n3 = 3 * n;
+    constexpr bool kCorr = std::is_same<S, float>::value;   // ssum holds C, not S
+    __shared__ double PtPs[kCorr ? kMaxCoef * kMaxCoef : 1], csum[kCorr ? kAxes * kMaxCoef : 1];
+    gptr<const double> cm = glob((const double*)Dp->c);
+    const int ldc = Dp->ldc;
+    const double nn = (double)(n + Dp->n_obs);
+    if constexpr (kCorr) {
+        // sum_j c_j per (axis, coefficient): agents j = grp, grp + ng, ... per group, then the
+        // groups in order
+        constexpr int kGroups = 7;
+        __shared__ double cpart[kGroups * kAxes * kMaxCoef];
+        gptr<const double> Gm = glob(Dp->PtP);
+        for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) PtPs[e] = Gm[e];
+        const int m3 = kAxes * nv;
+        const int ng = max(1, min(kGroups, (int)blockDim.x / m3));
+        for (int o = threadIdx.x; o < ng * m3; o += blockDim.x) {
+            const int grp = o / m3, al = o - grp * m3;
+            const int a = al / nv, l = al - a * nv;
+            gptr<const double> ca = cm + (size_t)a * ldc + l;
+            double sacc = 0.0;
+            for (int j = grp; j < n; j += ng) sacc += ca[(size_t)j * nv];
+            cpart[grp * m3 + al] = sacc;
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < m3; o += blockDim.x) {
+            double sacc = cpart[o];
+            for (int grp = 1; grp < ng; ++grp) sacc += cpart[grp * m3 + o];
+            csum[o] = sacc;
+        }
+        __syncthreads();
+    }
+    // row k of P^T P ((n + n_obs) c_i - sum_j c_j) for column (a, i)
+    auto xterm = [&](int a, int i, int k) {
+        gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * nv;
+        double v = 0.0;
+        for (int l = 0; l < nv; ++l) v += PtPs[k * nv + l] * (nn * ci[l] - csum[a * nv + l]);
+        return v;
+    };
     if constexpr (NV > 0) {
         // A thread owns columns tid and tid + 256 (3n <= 480); the basis rows are staged in
         // LDS in chunks and each column's S values are loaded 8 instants at a time.
@@ -1300,6 +1363,19 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
             if (col >= n3) continue;
             const int a = col / n, i = col - a * n;
             const size_t o = (size_t)a * ldq + (size_t)i * nv;
+            if constexpr (kCorr) {
+                gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * NV;
+                double v[NV];
+#pragma unroll
+                for (int l = 0; l < NV; ++l) v[l] = nn * ci[l] - csum[a * NV + l];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NV; ++l) x += PtPs[k * NV + l] * v[l];
+                    acc[h][k] += x;
+                }
+            }
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 q[o + k] = rho * acc[h][k];
@@ -1315,6 +1391,7 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
                 for (int t = 0; t < T; ++t) acc += Pm[(size_t)t * nv + k] * (double)sp[(size_t)t * n3];
+                if constexpr (kCorr) acc += xterm(a, i, k);
                 q[o + k] = rho * acc;
                 qf[o + k] = (float)(rho * acc);
             }
