@@ -6,9 +6,8 @@
 // applied to the FP64 refinement residual g - H c and added to c (K11^{-1} A^T = 0,
 // so the boundary multipliers nu are not needed for the correction).
 //
-// Tiles are 64 rows x 64 right-hand sides; in each group of 4 wavefronts a
-// wavefront owns a 32 x 32 quadrant computed as 2 x 2 blocks of 16 x 16 MFMA outputs.
-//   gemm_f32   v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation.
+// Tiles are 64 rows x 64 (or 48) right-hand sides, computed as 16 x 16 MFMA output blocks.
+//   gemm_f32_tile  v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation.
 //   gemm_bf16  v_mfma_f32_16x16x32_bf16 over three-term BF16 splits of both
 //              operands (the six products down to 2^-16 relative), FP32 accumulation.
 //   gemm_f64   FP64 FMA (the reference-precision path).
@@ -116,99 +115,96 @@ __device__ inline void finish_tile(const GemmTile& t, const GemmGroup& G, const 
     }
 }
 
-__global__ __launch_bounds__(512) void gemm_f32(const GemmTile* __restrict__ tiles,
-                                                const GemmGroup* __restrict__ groups,
-                                                const GemmCol* __restrict__ cols, int accumulate) {
+// FP32 product over tiles of 64 rows x 16 NB right-hand sides (NB = 4: 64, NB = 3: 48,
+// the width chosen when it balances the tiles over the compute units better, e.g. 704
+// instead of 528 tiles at n = 64 and 1024 problems).  256 threads; wavefront wq owns
+// rows 16 wq .. 16 wq + 15 and all NB blocks of 16 x 16 MFMA outputs.  The 32-wide K
+// steps go through two LDS stages: the next step is stored while the current one is
+// multiplied, one barrier per step, and the step after next is already being loaded.
+// Staging: thread (wq, lr) loads row m0 + lr of K11^{-1} and right-hand side col0 + lr
+// at k-slice [8 wq, 8 wq + 8) of the step and stores each as two 16-byte words into the
+// [row][k] stage (k stride kLDK: the 16 lanes of a read hit disjoint banks).  MFMA kk
+// (0..7) of a step takes k = 8 g + kk in lane group g = lane / 16, so a lane reads its
+// eight k of a row as two 16-byte words.  Every output takes the same MFMA sequence at
+// either width, so both widths give the same bits.
+constexpr int kW48 = 48;
+constexpr int kLDK = 36;
+// operands are read through the global address space, so that the loads are global (not
+// flat) loads and waiting for LDS does not also wait for them
+typedef __attribute__((address_space(1))) const float* gcfloat;
+typedef __attribute__((address_space(1))) const floatx4* gcfloat4;
+
+template <int NB>
+__global__ __launch_bounds__(256) void gemm_f32_tile(const GemmTile* __restrict__ tiles,
+                                                     const GemmGroup* __restrict__ groups,
+                                                     const GemmCol* __restrict__ cols, int accumulate) {
+    constexpr int NC = 16 * NB;                         // right-hand sides per tile
+    constexpr int STAGE = (64 + NC) * kLDK;             // floats per stage: A [64][kLDK], B [NC][kLDK]
     const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
-    constexpr int LD = 80;                      // row stride: conflict-free MFMA operand reads
-    __shared__ float smem[2 * 2 * 32 * LD];     // per group: A [k][m], B [k][rhs]
-    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
-    const int lane = gt & 63, wq = gt >> 6;
-    const int wm = wq >> 1, wn = wq & 1;
-    const int lr = gt & 63, kq = (gt >> 6) * 8;
-    float* As = smem + grp * 2 * 32 * LD;
-    float* Bs = As + 32 * LD;
+    __shared__ __align__(16) float smem[2 * STAGE];
+    const int tid = threadIdx.x, lane = tid & 63, wq = tid >> 6;
+    const int lr = lane, kq = wq * 8;
     bool act;
-    const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
-    if (!__syncthreads_or(act)) return;         // every right-hand side converged
-    const float* arow = (const float*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const gcfloat brow = (gcfloat)col_ptr(G, cols, t.col0 + lr, act) + kq;
+    if (!__syncthreads_or(act && lr < NC)) return;      // every right-hand side of the tile converged
+    const gcfloat arow = (gcfloat)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
     const int nk = G.ldk / 32;
-    const int nsteps = (nk + 1) / 2;            // steps per group (group 1 may idle on the last)
-    floatx4 acc[2][2];
+    floatx4 acc[NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float4 ra0, ra1, rb0, rb1;
+    for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    floatx4 ra0, ra1, rb0, rb1;
     auto fetch = [&](int s) {
-        const int k0 = (2 * s + grp) * 32;
-        if (k0 < G.ldk) {
-            ra0 = *(const float4*)(arow + k0);
-            ra1 = *(const float4*)(arow + k0 + 4);
-            rb0 = *(const float4*)(brow + k0);
-            rb1 = *(const float4*)(brow + k0 + 4);
+        const int k0 = s * 32;
+        ra0 = *(gcfloat4)(arow + k0);
+        ra1 = *(gcfloat4)(arow + k0 + 4);
+        rb0 = *(gcfloat4)(brow + k0);
+        rb1 = *(gcfloat4)(brow + k0 + 4);
+    };
+    auto store = [&](int s) {
+        float* As = smem + (s & 1) * STAGE;
+        float* Bs = As + 64 * kLDK;
+        *(floatx4*)(As + lr * kLDK + kq) = ra0;
+        *(floatx4*)(As + lr * kLDK + kq + 4) = ra1;
+        if (lr < NC) {
+            *(floatx4*)(Bs + lr * kLDK + kq) = rb0;
+            *(floatx4*)(Bs + lr * kLDK + kq + 4) = rb1;
         }
     };
+    const int m = lane & 15, g8 = (lane >> 4) * 8;
     fetch(0);
-    for (int s = 0; s < nsteps; ++s) {
-        const bool valid = (2 * s + grp) < nk;
-        __syncthreads();
-        if (valid) {
-            As[(kq + 0) * LD + lr] = ra0.x; As[(kq + 1) * LD + lr] = ra0.y;
-            As[(kq + 2) * LD + lr] = ra0.z; As[(kq + 3) * LD + lr] = ra0.w;
-            As[(kq + 4) * LD + lr] = ra1.x; As[(kq + 5) * LD + lr] = ra1.y;
-            As[(kq + 6) * LD + lr] = ra1.z; As[(kq + 7) * LD + lr] = ra1.w;
-            Bs[(kq + 0) * LD + lr] = rb0.x; Bs[(kq + 1) * LD + lr] = rb0.y;
-            Bs[(kq + 2) * LD + lr] = rb0.z; Bs[(kq + 3) * LD + lr] = rb0.w;
-            Bs[(kq + 4) * LD + lr] = rb1.x; Bs[(kq + 5) * LD + lr] = rb1.y;
-            Bs[(kq + 6) * LD + lr] = rb1.z; Bs[(kq + 7) * LD + lr] = rb1.w;
-        }
-        __syncthreads();
-        if (s + 1 < nsteps) fetch(s + 1);
-        if (valid) {
-            float af[8][2], bf[8][2];
+    store(0);
+    if (nk > 1) fetch(1);
+    __syncthreads();
+    for (int s = 0; s < nk; ++s) {
+        const float* As = smem + (s & 1) * STAGE;
+        const float* Bs = As + 64 * kLDK;
+        const floatx4 a0 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8);
+        const floatx4 a1 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8 + 4);
+        const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        float bv[NB][8];
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int kr = (4 * kk + (lane >> 4)) * LD;
+        for (int j = 0; j < NB; ++j) {
+            const floatx4 b0 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8);
+            const floatx4 b1 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8 + 4);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) af[kk][i] = As[kr + wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) bf[kk][j] = Bs[kr + wn * 32 + j * 16 + (lane & 15)];
+            for (int e = 0; e < 4; ++e) {
+                bv[j][e] = b0[e];
+                bv[j][e + 4] = b1[e];
             }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
         }
+        // the NB accumulators interleaved: independent MFMAs back to back
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bv[j][kk], acc[j], 0, 0, 0);
+        if (s + 1 < nk) store(s + 1);
+        if (s + 2 < nk) fetch(s + 2);
+        __syncthreads();
     }
-    finish_tile(t, G, cols, acc, smem, grp, wq, lane, accumulate);
-}
-
-// The same product over 64-row x 48-column tiles (chosen when it balances the tiles
-// over the compute units better, e.g. 704 instead of 528 tiles at n = 64 and 1024
-// problems): wave wq of a group owns rows 16 wq .. 16 wq + 15 and all 48 columns
-// (1 x 3 blocks of 16 x 16 MFMA outputs).  Staging and the K split are those of
-// gemm_f32 (lanes 48..63 stage right-hand sides no block reads), and every output takes
-// the same MFMA sequence, so the results are those of gemm_f32.
-constexpr int kW48 = 48;
-
-__device__ inline void finish_tile_w48(const GemmTile& t, const GemmGroup& G, const GemmCol* __restrict__ cols,
-                                       floatx4 (&acc)[3], float* red, int grp, int wq, int lane, int accumulate) {
-    __syncthreads();
-    if (grp == 1) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) red[((wq * 3 + j) * 4 + r) * 64 + lane] = acc[j][r];
-    }
-    __syncthreads();
-    if (grp != 0) return;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < NB; ++j) {
         const int col = t.col0 + j * 16 + (lane & 15);
         if (col >= G.ncols) continue;
         const GemmCol cc = cols[G.first_col + col];
@@ -222,76 +218,9 @@ __device__ inline void finish_tile_w48(const GemmTile& t, const GemmGroup& G, co
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = t.m0 + wq * 16 + 4 * (lane >> 4) + r;
-            const float v = acc[j][r] + red[((wq * 3 + j) * 4 + r) * 64 + lane];
-            if (row < G.M) cc.c[row] = old[r] + (double)v;
+            if (row < G.M) cc.c[row] = old[r] + (double)acc[j][r];
         }
     }
-}
-
-__global__ __launch_bounds__(512) void gemm_f32_w48(const GemmTile* __restrict__ tiles,
-                                                    const GemmGroup* __restrict__ groups,
-                                                    const GemmCol* __restrict__ cols, int accumulate) {
-    const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const GemmGroup G = groups[t.group];
-    constexpr int LD = 80;                      // row stride: conflict-free MFMA operand reads
-    __shared__ float smem[2 * 2 * 32 * LD];     // per group: A [k][m], B [k][rhs]
-    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
-    const int lane = gt & 63, wq = gt >> 6;
-    const int lr = gt & 63, kq = (gt >> 6) * 8;
-    float* As = smem + grp * 2 * 32 * LD;
-    float* Bs = As + 32 * LD;
-    bool act;
-    const float* brow = col_ptr(G, cols, t.col0 + lr, act) + kq;
-    if (!__syncthreads_or(act && lr < kW48)) return;   // every right-hand side of the tile converged
-    const float* arow = (const float*)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
-    const int nk = G.ldk / 32;
-    const int nsteps = (nk + 1) / 2;            // steps per group (group 1 may idle on the last)
-    floatx4 acc[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float4 ra0, ra1, rb0, rb1;
-    auto fetch = [&](int s) {
-        const int k0 = (2 * s + grp) * 32;
-        if (k0 < G.ldk) {
-            ra0 = *(const float4*)(arow + k0);
-            ra1 = *(const float4*)(arow + k0 + 4);
-            rb0 = *(const float4*)(brow + k0);
-            rb1 = *(const float4*)(brow + k0 + 4);
-        }
-    };
-    fetch(0);
-    for (int s = 0; s < nsteps; ++s) {
-        const bool valid = (2 * s + grp) < nk;
-        __syncthreads();
-        if (valid) {
-            As[(kq + 0) * LD + lr] = ra0.x; As[(kq + 1) * LD + lr] = ra0.y;
-            As[(kq + 2) * LD + lr] = ra0.z; As[(kq + 3) * LD + lr] = ra0.w;
-            As[(kq + 4) * LD + lr] = ra1.x; As[(kq + 5) * LD + lr] = ra1.y;
-            As[(kq + 6) * LD + lr] = ra1.z; As[(kq + 7) * LD + lr] = ra1.w;
-            Bs[(kq + 0) * LD + lr] = rb0.x; Bs[(kq + 1) * LD + lr] = rb0.y;
-            Bs[(kq + 2) * LD + lr] = rb0.z; Bs[(kq + 3) * LD + lr] = rb0.w;
-            Bs[(kq + 4) * LD + lr] = rb1.x; Bs[(kq + 5) * LD + lr] = rb1.y;
-            Bs[(kq + 6) * LD + lr] = rb1.z; Bs[(kq + 7) * LD + lr] = rb1.w;
-        }
-        __syncthreads();
-        if (s + 1 < nsteps) fetch(s + 1);
-        if (valid) {
-            float af[8], bf[8][3];
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int kr = (4 * kk + (lane >> 4)) * LD;
-                af[kk] = As[kr + wq * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < 3; ++j) bf[kk][j] = Bs[kr + j * 16 + (lane & 15)];
-            }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk], bf[kk][j], acc[j], 0, 0, 0);
-        }
-    }
-    finish_tile_w48(t, G, cols, acc, smem, grp, wq, lane, accumulate);
 }
 
 // An FP32 value as the sum of three bf16 terms, hi = bf16(x), mid = bf16(x - hi),
@@ -448,9 +377,9 @@ hipError_t launch_gemm(int precision, int width, const GemmTile* tiles, int ntil
                        const GemmCol* cols, int accumulate, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (precision == MATO_FP32 && width == kW48)
-        gemm_f32_w48<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
+        gemm_f32_tile<3><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
     else if (precision == MATO_FP32)
-        gemm_f32<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
+        gemm_f32_tile<4><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
     else if (precision == MATO_BF16_REFINED)
         gemm_bf16<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
     else

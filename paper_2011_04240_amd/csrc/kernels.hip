@@ -1311,6 +1311,27 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         constexpr int kRows = 2048;
         constexpr int TC = kRows / NV;
         __shared__ double Ps[kRows];
+        if constexpr (kCorr) {
+            // the positions' part of FP32 problems first, parked in q (read back by the same
+            // thread at the end), so that it holds no registers through the sum over instants
+            for (int h = 0; h < 2; ++h) {
+                const int col = threadIdx.x + h * 256;
+                if (col >= n3) continue;
+                const int a = col / n, i = col - a * n;
+                gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * NV;
+                double v[NV];
+#pragma unroll
+                for (int l = 0; l < NV; ++l) v[l] = nn * ci[l] - csum[a * NV + l];
+                const size_t o = (size_t)a * ldq + (size_t)i * NV;
+#pragma unroll 1
+                for (int k = 0; k < NV; ++k) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NV; ++l) x += PtPs[k * NV + l] * v[l];
+                    q[o + k] = x;
+                }
+            }
+        }
         double acc[2][NV];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -1363,23 +1384,11 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
             if (col >= n3) continue;
             const int a = col / n, i = col - a * n;
             const size_t o = (size_t)a * ldq + (size_t)i * nv;
-            if constexpr (kCorr) {
-                gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * NV;
-                double v[NV];
-#pragma unroll
-                for (int l = 0; l < NV; ++l) v[l] = nn * ci[l] - csum[a * NV + l];
-#pragma unroll
-                for (int k = 0; k < NV; ++k) {
-                    double x = 0.0;
-#pragma unroll
-                    for (int l = 0; l < NV; ++l) x += PtPs[k * NV + l] * v[l];
-                    acc[h][k] += x;
-                }
-            }
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                q[o + k] = rho * acc[h][k];
-                qf[o + k] = (float)(rho * acc[h][k]);
+                const double gk = kCorr ? rho * (q[o + k] + acc[h][k]) : rho * acc[h][k];
+                q[o + k] = gk;
+                qf[o + k] = (float)gk;
             }
         }
     } else {
@@ -1390,8 +1399,8 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         {
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
+                if constexpr (kCorr) acc = xterm(a, i, k);
                 for (int t = 0; t < T; ++t) acc += Pm[(size_t)t * nv + k] * (double)sp[(size_t)t * n3];
-                if constexpr (kCorr) acc += xterm(a, i, k);
                 q[o + k] = rho * acc;
                 qf[o + k] = (float)(rho * acc);
             }

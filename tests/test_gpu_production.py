@@ -12,7 +12,8 @@
 * Batching configuration: 256 problems with n uniform over {8, 12, ..., 48}, T = 100,
   FP32, autotuned tiles, 300 iterations in one batch; a sample of problems against the
   oracle's whole runs at 1e-3 relative on final cost, max ||f_c||, c and lambda (the
-  residual and multipliers relative to at least 1e-6, for problems that never collide).
+  multipliers relative to at least 1e-6, for problems that never collide; the residual
+  relative to at least 3.8e-3 m, where 1e-3 of it is 4 FP32 ulps of a position).
 * Serving configuration: dense inverse product in the BF16 split with FP64 corrections,
   fixed rho, stop at max ||f_c|| < 1e-3 m; each served result against the oracle run
   for the same number of iterations at 1e-3 relative (the final residual relative to at
@@ -47,6 +48,9 @@ def rel_floor(a, b, floor=1e-6):
 
 def say(*a):
     print(*a, flush=True)
+
+
+R_FP32 = 4 * 2.0 ** -20 / 1e-3      # m: 4 ulps of a coordinate in [8, 16) m, over the 1e-3 tolerance
 
 
 SCENES = {
@@ -117,8 +121,11 @@ def test_batching_config_against_oracle():
         ref = am.solve(am.make_plan(n, 100, 11, 10.0, 0.3, 0.6, 1.0), scen[q][0], scen[q][1], 300)
         r_max, r_rms, cost = b.residuals(q)
         st = b.get_state(q)
+        # max ||f_c|| is formed from FP32 positions: in the 10 m box they resolve 2^-20 m, and
+        # f_c = delta - d e carries a few such roundings, so the final residual is compared
+        # relative to at least R_FP32 (an absolute allowance of 4 position ulps at 1e-3)
         err = dict(cost=abs(cost[-1] - ref.history["cost"][-1]) / ref.history["cost"][-1],
-                   r_max=rel_floor(r_max[-1], ref.history["r_max"][-1]),
+                   r_max=rel_floor(r_max[-1], ref.history["r_max"][-1], floor=R_FP32),
                    c=rel(st["c"], ref.c), lam=rel_floor(st["lam"], ref.lam))
         say("  problem %d (n = %d)" % (q, n), {k: "%.2e" % v for k, v in err.items()})
         assert len(r_max) == 300
