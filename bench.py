@@ -9,13 +9,17 @@ stepped together (one batch's pairwise stage beside the other's per-problem
 kernels); the step as one batch on one stream is the default.
 
 Prints one JSON line: pair-timestep updates/s (n(n-1)/2 * T * B per step), the
-roofline of the pairwise kernel on the method's 24 bytes per pair-instant (every
-FP32 multiplier read and written back; the kernel writes back only the multipliers
-that change, so the line also gives the share of pair-instants that take the far-pair
-shortcut and of multipliers rewritten, the calibrated HBM counter bytes and their
-rate, and the multiplier reads against a measured streaming read), timed with HIP
-events on the stream of the batch, and the FP64 oracle timed on the host on a
-bounded sample (pool aggregate, and one problem on one thread).  Also in the line:
+roofline of the pairwise kernel, timed with HIP events on the stream of the batch,
+and the FP64 oracle timed on the host on a bounded sample (pool aggregate, and one
+problem on one thread).  The pairwise kernel reads a multiplier only where its 64-row
+group may hold a nonzero one and skips the rows whose agents' bounding boxes keep them
+clear over its instants, so it no longer streams the multipliers: the roofline is the
+vector ALU one on the dense step's arithmetic (55 FP32 flops per pair-instant, against
+the 157.3 TFLOP/s FP32 peak), with the instruction-issue share and the calibrated HBM
+counter bytes of the committed profile beside it, and the dense multiplier stream's
+24 bytes per pair-instant as a model (its rate above the 8 TB/s peak is traffic the
+kernel does not move), plus the branch census (pair-instants that take the far-pair
+shortcut, multipliers rewritten).  Also in the line:
 the same iteration on crowded, packed and n = 128 scenes, the structured x/y/z
 solve, served p50/p99 of the serving configuration (dense BF16 product with FP64
 corrections, n in 4..128, 10 / 100 / 500 requests/s) and of the structured variant,
@@ -36,8 +40,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector peak
+SIMD_ISSUE_PER_S = 1024 * 2.4e9 / 4   # wave64 VALU instructions per second: 1 024 SIMDs, 4 cycles each
+FLOPS_PER_UPDATE = 55            # FP32 flops of one dense pair-instant step (delta, s, d, projection, lambda, b_fc)
 BYTES_PER_UPDATE = 24            # every FP32 multiplier read and written back, as the method states the step
-READ_BYTES_PER_UPDATE = 12       # the multiplier reads alone (the kernel writes a multiplier only where it changes)
+READ_BYTES_PER_UPDATE = 12       # the multiplier reads alone
 PROFILES = os.path.join(ROOT, "profiles")
 
 # workloads of the pairwise stage: name -> (description, n, problems per launch, generator(n, seed))
@@ -123,22 +130,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(path):
-    """HBM bytes per pairwise launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source (else None)."""
+def counters_from_profile(path):
+    """Per pairwise launch, from committed rocprofv3 counters if they were taken on the
+    current kernel source: calibrated HBM bytes and wave64 VALU instructions (None where
+    absent or stale)."""
+    out = {"hbm_bytes_per_launch": None, "valu_insts_per_launch": None}
     if not os.path.exists(path):
-        return None
+        return out
     vals = {}
     for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return out
+    for k in out:
+        try:
+            out[k] = float(vals[k].split()[0])
+        except (KeyError, ValueError, IndexError):
+            pass
+    return out
 
 
 def _oracle_iterations(job):
@@ -692,7 +703,8 @@ def time_workload(name, T, steps, warmup, precision, solve, autotune=True, warm_
     """Iterations of B problems of one workload in one batch (eager launches, HIP events
     around every kernel on the batch's stream): seconds per step, the pairwise kernel's
     average launch, the branch census after the timed steps and the roofline of the
-    pairwise kernel on the method's 24 bytes per pair-instant."""
+    pairwise kernel (vector ALU on the dense step's 55 flops per pair-instant; the dense
+    multiplier stream's 24 bytes per pair-instant as a model)."""
     import torch
     from paper_2011_04240_amd import mato
     desc, n, B, _ = WORKLOADS[name]
@@ -720,17 +732,26 @@ def time_workload(name, T, steps, warmup, precision, solve, autotune=True, warm_
     census = branch_census(batch, list(range(min(8, B))), n)
     batch.close()
     plan.close()
-    achieved = BYTES_PER_UPDATE * units / pw_avg_s / 1e9
-    traffic = traffic_from_counters(counters_file(name, n, T, B))
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "pairwise_kernel", "avg_launch_ms": pw_avg_s * 1e3,
-            "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * units,
-            "bytes_per_unit": BYTES_PER_UPDATE, "units_per_launch": units,
+    achieved = FLOPS_PER_UPDATE * units / pw_avg_s / 1e12
+    prof = counters_from_profile(counters_file(name, n, T, B))
+    traffic = prof["hbm_bytes_per_launch"]
+    dense_GBps = BYTES_PER_UPDATE * units / pw_avg_s / 1e9
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": "pairwise_fx_kernel" if precision != "fp64" else "pairwise_kernel",
+            "avg_launch_ms": pw_avg_s * 1e3,
+            "flops_per_unit": FLOPS_PER_UPDATE, "algorithmic_flops_per_launch": FLOPS_PER_UPDATE * units,
+            "units_per_launch": units,
+            "hbm_model": {"bytes_per_unit": BYTES_PER_UPDATE,
+                          "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * units,
+                          "achieved_GBps": dense_GBps, "frac_of_peak": dense_GBps / HBM_PEAK_GBS},
             "shortcut_frac": census["shortcut_frac"], "written_frac": census["written_frac"]}
     if traffic is not None:
         roof["traffic_GBps"] = traffic / pw_avg_s / 1e9
         roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
+    if prof["valu_insts_per_launch"] is not None:
+        roof["valu_insts_per_launch"] = prof["valu_insts_per_launch"]
+        roof["valu_issue_frac"] = prof["valu_insts_per_launch"] / SIMD_ISSUE_PER_S / pw_avg_s
     return {"workload": desc, "name": name, "n": n, "T": T, "problems": B, "precision": precision, "solve": solve,
             "ms_per_step": wall / steps * 1e3, "updates_per_s": units * steps / wall,
             "device_ms_per_step": total_ms / steps, "plan_s": plan_s,
@@ -756,10 +777,12 @@ def run_main(args, pool):
     stream_rd = stream_ceiling(read_bytes, "read")
     stream = stream_ceiling(read_bytes)
     stream_upd = stream_ceiling(read_bytes, "update")
-    roof.update({"stream_read": stream_rd, "stream_copy": stream, "stream_update": stream_upd,
-                 "read_bytes_per_launch": read_bytes,
-                 "read_GBps": read_bytes / (roof["avg_launch_ms"] * 1e-3) / 1e9})
-    roof["read_frac_of_stream_read"] = roof["read_GBps"] / stream_rd["GBps"]
+    # the streaming probes over the dense multiplier array: the rate a multiplier stream
+    # would reach (context for the model; the kernel reads only flagged groups)
+    roof["hbm_model"].update({"stream_read": stream_rd, "stream_copy": stream, "stream_update": stream_upd,
+                              "read_bytes_per_launch": read_bytes,
+                              "read_GBps": read_bytes / (roof["avg_launch_ms"] * 1e-3) / 1e9})
+    roof["hbm_model"]["read_frac_of_stream_read"] = roof["hbm_model"]["read_GBps"] / stream_rd["GBps"]
     if roof["traffic"] is not None:
         roof["traffic_frac_of_stream_read"] = roof["traffic_GBps"] / stream_rd["GBps"]
     single = {"ms_per_step": head["ms_per_step"], "updates_per_s": head["updates_per_s"]}

@@ -337,7 +337,7 @@ static mato_status set_state_impl(BatchImpl<S>* B, int q, const double* c, const
     if (c) MATO_HIP(launch_positions<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
     MATO_HIP(launch_pairwise<S>(ditems, (int)items.size(), dd, kModeSetState, B->threads, B->lds, B->common_nv(), true,
                                 B->stream));
-    MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), B->stream));
+    MATO_HIP(launch_qbuild<S>(dd, 1, kModeInit, B->common_nv(), P.n, B->stream));
     MATO_HIP(hipStreamSynchronize(B->stream));
     return MATO_OK;
 }

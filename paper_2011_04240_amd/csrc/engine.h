@@ -32,7 +32,7 @@ hipError_t launch_pairwise(const WorkItem*, int, const ProblemDesc<S>*, int, int
 template <typename S>
 hipError_t set_pairwise_lds_limit(size_t);
 template <typename S>
-hipError_t launch_qbuild(const ProblemDesc<S>*, int, int, int, hipStream_t);
+hipError_t launch_qbuild(const ProblemDesc<S>*, int, int, int, int, hipStream_t);
 template <typename S>
 hipError_t launch_residual(const ProblemDesc<S>*, int, hipStream_t);
 template <typename S>
@@ -272,6 +272,13 @@ struct Engine {
             if (P.nv != nv) return 0;
         }
         return nv < 0 ? 0 : nv;
+    }
+
+    // largest agent count among the slots (sizes the linear-term kernel's LDS)
+    int max_agents() const {
+        int m = 1;
+        for (const auto& P : probs) m = std::max(m, P.n);
+        return m;
     }
 
     // ------------------------------------------------------------ layout ---
@@ -678,7 +685,7 @@ struct Engine {
         MATO_HIP(launch_ceq<S>(ddesc, dkinv, count(), stream));
         MATO_HIP(launch_positions<S>(ddesc, count(), kModeInit, nv, stream));
         MATO_HIP(launch_pairwise<S>(ditems, (int)hitems.size(), ddesc, kModeInit, threads, lds, nv, has_obs, stream));
-        MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, nv, stream));
+        MATO_HIP(launch_qbuild<S>(ddesc, count(), kModeInit, nv, max_agents(), stream));
         return MATO_OK;
     }
 
@@ -702,7 +709,7 @@ struct Engine {
         MATO_HIP(launch_ceq<S>(d, dkinv + q, 1, stream));
         MATO_HIP(launch_positions<S>(d, 1, kModeInit, nv, stream));
         MATO_HIP(launch_pairwise<S>(dscratch, (int)items.size(), d, kModeInit, threads, std::max(l, lds), nv, has_obs, stream));
-        MATO_HIP(launch_qbuild<S>(d, 1, kModeInit, nv, stream));
+        MATO_HIP(launch_qbuild<S>(d, 1, kModeInit, nv, probs[q].n, stream));
         return MATO_OK;
     }
 
@@ -744,7 +751,7 @@ struct Engine {
             if (e != hipSuccess) return e;
             pw_used += 2;
         }
-        return launch_qbuild<S>(ddesc, count(), kModeIter, nv, st);
+        return launch_qbuild<S>(ddesc, count(), kModeIter, nv, max_agents(), st);
     }
 
     void drop_graphs() {

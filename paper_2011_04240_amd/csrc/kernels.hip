@@ -1268,42 +1268,56 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
     gptr<float> qf = glob(Dp->qf);
     const int n3 = 3 * n;
     constexpr bool kCorr = std::is_same<S, float>::value;   // ssum holds C, not S
+    // FP32 problems: the positions' part P^T P ((n + n_obs) c_i - sum_j c_j) per column, from the
+    // columns' coefficients staged in LDS (dynamic, [3n][nv]), which then hold the part itself
+    extern __shared__ double cxs[];
     __shared__ double PtPs[kCorr ? kMaxCoef * kMaxCoef : 1], csum[kCorr ? kAxes * kMaxCoef : 1];
-    gptr<const double> cm = glob((const double*)Dp->c);
-    const int ldc = Dp->ldc;
-    const double nn = (double)(n + Dp->n_obs);
     if constexpr (kCorr) {
-        // sum_j c_j per (axis, coefficient): agents j = grp, grp + ng, ... per group, then the
-        // groups in order
+        gptr<const double> cm = glob((const double*)Dp->c);
+        gptr<const double> Gm = glob(Dp->PtP);
+        const int ldc = Dp->ldc;
+        const double nn = (double)(n + Dp->n_obs);
+        for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) PtPs[e] = Gm[e];
+        for (int e = threadIdx.x; e < n3 * nv; e += blockDim.x) {
+            const int col = e / nv, l = e - col * nv, a = col / n, i = col - a * n;
+            cxs[e] = cm[(size_t)a * ldc + (size_t)i * nv + l];
+        }
+        __syncthreads();
+        // sum over agents: groups of agents g, g + 7, ... first, then the groups in order
         constexpr int kGroups = 7;
         __shared__ double cpart[kGroups * kAxes * kMaxCoef];
-        gptr<const double> Gm = glob(Dp->PtP);
-        for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) PtPs[e] = Gm[e];
         const int m3 = kAxes * nv;
-        const int ng = max(1, min(kGroups, (int)blockDim.x / m3));
-        for (int o = threadIdx.x; o < ng * m3; o += blockDim.x) {
+        for (int o = threadIdx.x; o < kGroups * m3; o += blockDim.x) {
             const int grp = o / m3, al = o - grp * m3;
             const int a = al / nv, l = al - a * nv;
-            gptr<const double> ca = cm + (size_t)a * ldc + l;
             double sacc = 0.0;
-            for (int j = grp; j < n; j += ng) sacc += ca[(size_t)j * nv];
-            cpart[grp * m3 + al] = sacc;
+            for (int i = grp; i < n; i += kGroups) sacc += cxs[((size_t)a * n + i) * nv + l];
+            cpart[o] = sacc;
         }
         __syncthreads();
         for (int o = threadIdx.x; o < m3; o += blockDim.x) {
             double sacc = cpart[o];
-            for (int grp = 1; grp < ng; ++grp) sacc += cpart[grp * m3 + o];
+            for (int grp = 1; grp < kGroups; ++grp) sacc += cpart[grp * m3 + o];
             csum[o] = sacc;
         }
         __syncthreads();
+        constexpr int NVC = NV > 0 ? NV : kMaxCoef;
+        for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+            const int a = col / n;
+            double* cc = cxs + (size_t)col * nv;
+            double v[NVC];
+#pragma unroll
+            for (int l = 0; l < NVC; ++l) v[l] = (NV > 0 || l < nv) ? nn * cc[l] - csum[a * nv + l] : 0.0;
+#pragma unroll 1
+            for (int k = 0; k < nv; ++k) {
+                double x = 0.0;
+#pragma unroll
+                for (int l = 0; l < NVC; ++l)
+                    if (NV > 0 || l < nv) x += PtPs[k * nv + l] * v[l];
+                cc[k] = x;                               // own column only: no other thread reads it
+            }
+        }
     }
-    // row k of P^T P ((n + n_obs) c_i - sum_j c_j) for column (a, i)
-    auto xterm = [&](int a, int i, int k) {
-        gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * nv;
-        double v = 0.0;
-        for (int l = 0; l < nv; ++l) v += PtPs[k * nv + l] * (nn * ci[l] - csum[a * nv + l]);
-        return v;
-    };
     if constexpr (NV > 0) {
         // A thread owns columns tid and tid + 256 (3n <= 480); the basis rows are staged in
         // LDS in chunks and each column's S values are loaded 8 instants at a time.
@@ -1311,27 +1325,6 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         constexpr int kRows = 2048;
         constexpr int TC = kRows / NV;
         __shared__ double Ps[kRows];
-        if constexpr (kCorr) {
-            // the positions' part of FP32 problems first, parked in q (read back by the same
-            // thread at the end), so that it holds no registers through the sum over instants
-            for (int h = 0; h < 2; ++h) {
-                const int col = threadIdx.x + h * 256;
-                if (col >= n3) continue;
-                const int a = col / n, i = col - a * n;
-                gptr<const double> ci = cm + (size_t)a * ldc + (size_t)i * NV;
-                double v[NV];
-#pragma unroll
-                for (int l = 0; l < NV; ++l) v[l] = nn * ci[l] - csum[a * NV + l];
-                const size_t o = (size_t)a * ldq + (size_t)i * NV;
-#pragma unroll 1
-                for (int k = 0; k < NV; ++k) {
-                    double x = 0.0;
-#pragma unroll
-                    for (int l = 0; l < NV; ++l) x += PtPs[k * NV + l] * v[l];
-                    q[o + k] = x;
-                }
-            }
-        }
         double acc[2][NV];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -1386,7 +1379,7 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
             const size_t o = (size_t)a * ldq + (size_t)i * nv;
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                const double gk = kCorr ? rho * (q[o + k] + acc[h][k]) : rho * acc[h][k];
+                const double gk = kCorr ? rho * (cxs[(size_t)col * NV + k] + acc[h][k]) : rho * acc[h][k];
                 q[o + k] = gk;
                 qf[o + k] = (float)gk;
             }
@@ -1399,7 +1392,7 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
         {
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
-                if constexpr (kCorr) acc = xterm(a, i, k);
+                if constexpr (kCorr) acc = cxs[(size_t)col * nv + k];
                 for (int t = 0; t < T; ++t) acc += Pm[(size_t)t * nv + k] * (double)sp[(size_t)t * n3];
                 q[o + k] = rho * acc;
                 qf[o + k] = (float)(rho * acc);
@@ -1712,12 +1705,14 @@ hipError_t set_pairwise_lds_limit(size_t lds) {
 }
 
 template <typename S>
-hipError_t launch_qbuild(const ProblemDesc<S>* probs, int nprob, int mode, int nv, hipStream_t st) {
+hipError_t launch_qbuild(const ProblemDesc<S>* probs, int nprob, int mode, int nv, int nmax, hipStream_t st) {
     if (nprob <= 0) return hipSuccess;
+    // FP32: the coefficients of every (axis, agent) column of the largest problem in LDS
+    const size_t lds = std::is_same<S, float>::value ? sizeof(double) * 3 * (size_t)nmax * (nv > 0 ? nv : kMaxCoef) : 0;
     if (nv == 11)
-        qbuild_kernel<S, 11><<<nprob, 256, 0, st>>>(probs, mode);
+        qbuild_kernel<S, 11><<<nprob, 256, lds, st>>>(probs, mode);
     else
-        qbuild_kernel<S, 0><<<nprob, 256, 0, st>>>(probs, mode);
+        qbuild_kernel<S, 0><<<nprob, 256, lds, st>>>(probs, mode);
     return hipGetLastError();
 }
 
@@ -1768,8 +1763,8 @@ template hipError_t launch_pairwise<double>(const WorkItem*, int, const ProblemD
                                            hipStream_t);
 template hipError_t set_pairwise_lds_limit<float>(size_t);
 template hipError_t set_pairwise_lds_limit<double>(size_t);
-template hipError_t launch_qbuild<float>(const ProblemDesc<float>*, int, int, int, hipStream_t);
-template hipError_t launch_qbuild<double>(const ProblemDesc<double>*, int, int, int, hipStream_t);
+template hipError_t launch_qbuild<float>(const ProblemDesc<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_qbuild<double>(const ProblemDesc<double>*, int, int, int, int, hipStream_t);
 template hipError_t launch_positions<float>(const ProblemDesc<float>*, int, int, int, hipStream_t);
 template hipError_t launch_positions<double>(const ProblemDesc<double>*, int, int, int, hipStream_t);
 template hipError_t launch_residual<float>(const ProblemDesc<float>*, int, hipStream_t);
