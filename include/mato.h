@@ -243,7 +243,9 @@ mato_status mato_batch_set_rho_schedule(mato_batch batch, int32_t stages, const 
 mato_status mato_batch_set_projection(mato_batch batch, int32_t mode);
 
 /* Pairwise-stage launch shape: pair-instants per workgroup (target) and threads per
- * workgroup (256, 512 or 1024).  mato_batch_autotune times candidate shapes on the
+ * workgroup (256, 512 or 1024).  Until set: 16384 and 256, with work items shortened so
+ * that a batch of few problems still has about four per compute unit.
+ * mato_batch_autotune times candidate shapes on the
  * batch's own problems before it is used (state is re-initialised afterwards) and
  * keeps the fastest; results are cached in the file named by MATO_TUNE_CACHE.  */
 mato_status mato_batch_set_tiles(mato_batch batch, int32_t items_per_wg, int32_t threads);

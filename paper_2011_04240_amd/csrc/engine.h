@@ -138,7 +138,11 @@ struct Engine {
     size_t ditems_cap = 0;
     WorkItem* dscratch = nullptr;            // work items of one slot (initialisation, set-state)
     size_t dscratch_cap = 0;
-    int items_per_wg = 2048, threads = 256;
+    // pairwise launch shape until set or tuned: about 8 instants per work item at n = 64, so
+    // that the FP32 kernel's per-item work (positions, boxes, broad phase) spreads over them
+    int items_per_wg = 16384, threads = 256;
+    bool tiles_set = false;                  // set_tiles / autotune chose the shape
+    int n_active = 0;                        // active slots when the work list was built
     size_t lds = 0;
 
     std::vector<GemmGroup> hgroups;
@@ -416,6 +420,11 @@ struct Engine {
         const size_t fixed = pairwise_lds_fixed(P, threads);
         int tc = std::max(1, items_per_wg / std::max(1, P.np));
         tc = std::min(tc, P.T);
+        if (!tiles_set) {
+            // a few problems: keep about four work items per compute unit rather than long ones
+            const long want = 4L * device_cu_count();
+            tc = std::min(tc, std::max(1, (int)((long)P.T * std::max(1, n_active) / want)));
+        }
         while (tc > 1 && per_t * tc + fixed > (size_t)cap) --tc;
         *maxlds = std::max(*maxlds, per_t * tc + fixed);
         P.nslab = (P.T + tc - 1) / tc;
@@ -469,6 +478,8 @@ struct Engine {
         size_t maxlds = 0;
         has_obs = false;
         for (const auto& P : probs) has_obs = has_obs || (P.active && P.n_obs > 0);
+        n_active = 0;
+        for (const auto& P : probs) n_active += P.active ? 1 : 0;
         for (int q = 0; q < count(); ++q)
             if (probs[q].active) slot_items(q, hitems, &maxlds, q);
         lds = maxlds;
@@ -916,6 +927,7 @@ struct Engine {
         MATO_HIP(hipStreamSynchronize(stream));
         items_per_wg = ipw;
         threads = thr;
+        tiles_set = true;
         return rebuild_lists();
     }
 

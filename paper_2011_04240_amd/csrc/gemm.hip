@@ -117,10 +117,13 @@ __device__ inline void finish_tile(const GemmTile& t, const GemmGroup& G, const 
 
 // FP32 product over tiles of 64 rows x 16 NB right-hand sides (NB = 4: 64, NB = 3: 48,
 // the width chosen when it balances the tiles over the compute units better, e.g. 704
-// instead of 528 tiles at n = 64 and 1024 problems).  256 threads; wavefront wq owns
-// rows 16 wq .. 16 wq + 15 and all NB blocks of 16 x 16 MFMA outputs.  The 32-wide K
-// steps go through two LDS stages: the next step is stored while the current one is
-// multiplied, one barrier per step, and the step after next is already being loaded.
+// instead of 528 tiles at n = 64 and 1024 problems).  Wavefront wq of a group of four owns
+// rows 16 wq .. 16 wq + 15 and all NB blocks of 16 x 16 MFMA outputs.  The 32-wide K steps
+// go through two LDS stages: the next step is stored while the current one is multiplied,
+// one barrier per step, and the step after next is already being loaded.  The even and
+// the odd K steps accumulate apart and are added at the end, so that NG = 2 groups of
+// four wavefronts (512 threads, one group per parity: half the chain of steps, for
+// launches with fewer tiles than compute units) and NG = 1 give the same bits.
 // Staging: thread (wq, lr) loads row m0 + lr of K11^{-1} and right-hand side col0 + lr
 // at k-slice [8 wq, 8 wq + 8) of the step and stores each as two 16-byte words into the
 // [row][k] stage (k stride kLDK: the 16 lanes of a read hit disjoint banks).  MFMA kk
@@ -134,35 +137,41 @@ constexpr int kLDK = 36;
 typedef __attribute__((address_space(1))) const float* gcfloat;
 typedef __attribute__((address_space(1))) const floatx4* gcfloat4;
 
-template <int NB>
-__global__ __launch_bounds__(256) void gemm_f32_tile(const GemmTile* __restrict__ tiles,
-                                                     const GemmGroup* __restrict__ groups,
-                                                     const GemmCol* __restrict__ cols, int accumulate) {
+template <int NB, int NG>
+__global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __restrict__ tiles,
+                                                          const GemmGroup* __restrict__ groups,
+                                                          const GemmCol* __restrict__ cols, int accumulate) {
     constexpr int NC = 16 * NB;                         // right-hand sides per tile
     constexpr int STAGE = (64 + NC) * kLDK;             // floats per stage: A [64][kLDK], B [NC][kLDK]
+    constexpr int NA = 3 - NG;                          // accumulator sets per wavefront: 2 (NG = 1) or 1
     const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
-    __shared__ __align__(16) float smem[2 * STAGE];
-    const int tid = threadIdx.x, lane = tid & 63, wq = tid >> 6;
+    __shared__ __align__(16) float smem[NG * 2 * STAGE];
+    const int tid = threadIdx.x, grp = NG == 2 ? tid >> 8 : 0, gt = tid & 255;
+    const int lane = gt & 63, wq = gt >> 6;
     const int lr = lane, kq = wq * 8;
+    float* stg = smem + grp * 2 * STAGE;
     bool act;
     const gcfloat brow = (gcfloat)col_ptr(G, cols, t.col0 + lr, act) + kq;
     if (!__syncthreads_or(act && lr < NC)) return;      // every right-hand side of the tile converged
     const gcfloat arow = (gcfloat)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
     const int nk = G.ldk / 32;
-    floatx4 acc[NB];
+    const int nsteps = (nk + NG - 1) / NG;              // steps per group (group 1 may idle on the last)
+    floatx4 acc[NA][NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int h = 0; h < NA; ++h)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[h][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     floatx4 ra0, ra1, rb0, rb1;
-    auto fetch = [&](int s) {
-        const int k0 = s * 32;
+    auto fetch = [&](int s) {                            // group step s is K step NG s + grp
+        const int k0 = min(NG * s + grp, nk - 1) * 32;   // past the last: reload it (unused)
         ra0 = *(gcfloat4)(arow + k0);
         ra1 = *(gcfloat4)(arow + k0 + 4);
         rb0 = *(gcfloat4)(brow + k0);
         rb1 = *(gcfloat4)(brow + k0 + 4);
     };
     auto store = [&](int s) {
-        float* As = smem + (s & 1) * STAGE;
+        float* As = stg + (s & 1) * STAGE;
         float* Bs = As + 64 * kLDK;
         *(floatx4*)(As + lr * kLDK + kq) = ra0;
         *(floatx4*)(As + lr * kLDK + kq + 4) = ra1;
@@ -171,14 +180,10 @@ __global__ __launch_bounds__(256) void gemm_f32_tile(const GemmTile* __restrict_
             *(floatx4*)(Bs + lr * kLDK + kq + 4) = rb1;
         }
     };
-    const int m = lane & 15, g8 = (lane >> 4) * 8;
-    fetch(0);
-    store(0);
-    if (nk > 1) fetch(1);
-    __syncthreads();
-    for (int s = 0; s < nk; ++s) {
-        const float* As = smem + (s & 1) * STAGE;
+    auto mult = [&](int s, floatx4 (&ac)[NB]) {
+        const float* As = stg + (s & 1) * STAGE;
         const float* Bs = As + 64 * kLDK;
+        const int m = lane & 15, g8 = (lane >> 4) * 8;
         const floatx4 a0 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8);
         const floatx4 a1 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8 + 4);
         const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
@@ -198,10 +203,33 @@ __global__ __launch_bounds__(256) void gemm_f32_tile(const GemmTile* __restrict_
         for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
             for (int j = 0; j < NB; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bv[j][kk], acc[j], 0, 0, 0);
-        if (s + 1 < nk) store(s + 1);
-        if (s + 2 < nk) fetch(s + 2);
+                ac[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bv[j][kk], ac[j], 0, 0, 0);
+    };
+    fetch(0);
+    store(0);
+    if (nsteps > 1) fetch(1);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        if (NG == 1 || NG * s + grp < nk) {
+            if (NA == 2 && (s & 1)) mult(s, acc[NA - 1]);
+            else mult(s, acc[0]);
+        }
+        if (s + 1 < nsteps) store(s + 1);
+        if (s + 2 < nsteps) fetch(s + 2);
         __syncthreads();
+    }
+    // the odd steps' partial tile: the second accumulator set, or group 1's through LDS (the
+    // stages are free after the last barrier); even + odd, then c (+)= result
+    float* red = smem;
+    if (NG == 2) {
+        if (grp == 1) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[((wq * NB + j) * 4 + r) * 64 + lane] = acc[0][j][r];
+        }
+        __syncthreads();
+        if (grp != 0) return;
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -218,7 +246,9 @@ __global__ __launch_bounds__(256) void gemm_f32_tile(const GemmTile* __restrict_
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = t.m0 + wq * 16 + 4 * (lane >> 4) + r;
-            if (row < G.M) cc.c[row] = old[r] + (double)acc[j][r];
+            const float odd = NG == 2 ? red[((wq * NB + j) * 4 + r) * 64 + lane] : acc[NA - 1][j][r];
+            const float v = acc[0][j][r] + odd;
+            if (row < G.M) cc.c[row] = old[r] + (double)v;
         }
     }
 }
@@ -373,13 +403,29 @@ __global__ __launch_bounds__(256) void gemm_f64(const GemmTile* __restrict__ til
         for (int j = 0; j < 4; ++j) store_out(G, cols, t.m0 + tr + i, t.col0 + tcol + j, acc[i][j], accumulate);
 }
 
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 hipError_t launch_gemm(int precision, int width, const GemmTile* tiles, int ntiles, const GemmGroup* groups,
                        const GemmCol* cols, int accumulate, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (precision == MATO_FP32 && width == kW48)
-        gemm_f32_tile<3><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
-    else if (precision == MATO_FP32)
-        gemm_f32_tile<4><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
+    // fewer tiles than compute units: two groups of wavefronts per tile, one per K parity
+    const bool split = ntiles < device_cus();
+    if (precision == MATO_FP32 && width == kW48) {
+        if (split) gemm_f32_tile<3, 2><<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
+        else gemm_f32_tile<3, 1><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
+    } else if (precision == MATO_FP32) {
+        if (split) gemm_f32_tile<4, 2><<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
+        else gemm_f32_tile<4, 1><<<ntiles, 256, 0, st>>>(tiles, groups, cols, accumulate);
+    }
     else if (precision == MATO_BF16_REFINED)
         gemm_bf16<<<ntiles, 512, 0, st>>>(tiles, groups, cols, accumulate);
     else
