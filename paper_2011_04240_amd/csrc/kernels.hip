@@ -817,12 +817,20 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     bool use_list = false;
     if (MODE == kModeIter && !shifted && !dbg_on) {
         constexpr int nw = BLOCK / 64;
+        constexpr int kPre = 8;                        // groups whose pair codes are loaded together
         int cntw = 0;
-        for (int g = wv; g < ngr; g += nw) {
+        for (int g0 = wv; g0 < ngr; g0 += nw * kPre) {
+          unsigned cds[kPre];
+#pragma unroll
+          for (int k = 0; k < kPre; ++k) cds[k] = pairs[min(((g0 + k * nw) << 6) + lane, np - 1)];   // past np: unused
+#pragma unroll
+          for (int k = 0; k < kPre; ++k) {
+            const int g = g0 + k * nw;
+            if (g >= ngr) break;                       // uniform
             const int p = (g << 6) + lane;
             bool fail = false;
             if (p < np) {
-                const unsigned cd = pairs[p];
+                const unsigned cd = cds[k];
                 const int i = (int)(cd & 0xffffu), j = (int)(cd >> 16);
                 const S* bi = Bs + i * 6;
                 S gx, gy, gz, ia2p = ia2, ib2p = ib2;
@@ -845,6 +853,7 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             const unsigned long long b = __ballot(fail);
             if (lane == 0) Fb[g] = b;
             cntw += __popcll(b);
+          }
         }
         if (lane == 0) wcnt[wv] = cntw;
         __syncthreads();
