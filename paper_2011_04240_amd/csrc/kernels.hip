@@ -1079,18 +1079,25 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
             __builtin_amdgcn_wave_barrier();
             R = 0;
         };
-        for (int g = wv; g < ngr; g += nw) {
-            const unsigned long long mask = Fb[g];
-            if (mask == 0ull) continue;                                 // uniform
-            const int m = __popcll(mask);
-            if (R + m > 64) run_batch();
-            if ((mask >> lane) & 1ull) {
-                const int pos = R + __popcll(mask & ((1ull << lane) - 1ull));
-                const int p = (g << 6) + lane;
-                lq[2 * pos] = (unsigned)p;
-                lq[2 * pos + 1] = pairs[p];
+        constexpr int kPre = 8;                        // groups whose pair codes are loaded together
+        for (int g0 = wv; g0 < ngr; g0 += nw * kPre) {
+            unsigned cds[kPre];
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) cds[k] = pairs[min(((g0 + k * nw) << 6) + lane, np - 1)];   // past np: unused
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) {
+                const int g = g0 + k * nw;
+                const unsigned long long mask = g < ngr ? Fb[g] : 0ull;
+                if (mask == 0ull) continue;                             // uniform
+                const int m = __popcll(mask);
+                if (R + m > 64) run_batch();
+                if ((mask >> lane) & 1ull) {
+                    const int pos = R + __popcll(mask & ((1ull << lane) - 1ull));
+                    lq[2 * pos] = (unsigned)((g << 6) + lane);
+                    lq[2 * pos + 1] = cds[k];
+                }
+                R += m;
             }
-            R += m;
         }
         if (R > 0) run_batch();
     }
