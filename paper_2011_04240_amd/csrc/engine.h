@@ -147,7 +147,7 @@ struct Engine {
 
     std::vector<GemmGroup> hgroups;
     std::vector<GemmTile> htiles;
-    int gemm_width = 64;                     // right-hand sides per product tile (64, or 48 in FP32)
+    int gemm_width = 64;                     // right-hand sides per product tile (64, or 48 in FP32 and BF16)
     GemmGroup* dgroups = nullptr;
     GemmTile* dtiles = nullptr;
     GemmCol* dcolsq = nullptr;
@@ -506,10 +506,10 @@ struct Engine {
         std::vector<GemmCol> colq, colr;
         hgroups.clear();
         htiles.clear();
-        // tile width: 64 right-hand sides, or 48 in FP32 when that lowers the number of
+        // tile width: 64 right-hand sides, or 48 (FP32, BF16) when that lowers the number of
         // tiles the busiest compute unit works through times the tile's work
         gemm_width = 64;
-        if (precision == MATO_FP32) {
+        if (precision != MATO_FP64) {
             auto makespan = [&](int w) {
                 long tiles = 0;
                 for (const mato_plan pl : order)

@@ -113,13 +113,15 @@ def test_large_batch_uploads_match_alone_bitwise():
         np.testing.assert_array_equal(alone.residuals(0)[0], mix.residuals(q)[0])
 
 
-def test_product_tile_widths_agree_bitwise():
-    """The FP32 inverse product over 64-column tiles (chosen for this large batch of small
-    problems) and over 48-column tiles (chosen for one problem alone) gives the same
-    coefficients bit for bit."""
-    say("product tile widths")
-    n, count = 8, 2560
-    plan = mato.Plan(n, 20, 11, 5.0, 0.3, 0.6, 1.0, "fp32")
+@pytest.mark.parametrize("precision,count", [("fp32", 2560), ("fp32", 4096), ("bf16", 2560), ("bf16", 4096)])
+def test_product_tile_widths_agree_bitwise(precision, count):
+    """The FP32 and the BF16 inverse products give the same coefficients bit for bit whatever
+    the tile form: 2560 problems of n = 8 take 64-column tiles with two groups of wavefronts
+    (240 tiles, fewer than compute units), 4096 take 48-column tiles with one group (512
+    tiles), and one problem alone takes 48-column tiles with two groups."""
+    say("product tile widths", precision, count)
+    n = 8
+    plan = mato.Plan(n, 20, 11, 5.0, 0.3, 0.6, 1.0, precision)
     scen = [sc.random_density_box(n, seed=900 + q) for q in range(count)]
     big = mato.Batch([plan] * count, [x[0] for x in scen], [x[1] for x in scen])
     big.step(6, use_graph=False)
