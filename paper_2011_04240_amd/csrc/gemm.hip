@@ -109,18 +109,18 @@ __device__ inline void store_tile(const GemmTile& t, const GemmGroup& G, const C
 // FP32 product over tiles of 64 rows x 16 NB right-hand sides (NB = 4: 64, NB = 3: 48,
 // the width chosen when it balances the tiles over the compute units better, e.g. 704
 // instead of 528 tiles at n = 64 and 1024 problems).  Wavefront wq of a group of four owns
-// rows 16 wq .. 16 wq + 15 and all NB blocks of 16 x 16 MFMA outputs.  The 32-wide K steps
-// go through two LDS stages: the next step is stored while the current one is multiplied,
-// one barrier per step, and the step after next is already being loaded.  The even and
-// the odd K steps accumulate apart and are added at the end, so that NG = 2 groups of
-// four wavefronts (512 threads, one group per parity: half the chain of steps, for
-// launches with fewer tiles than compute units) and NG = 1 give the same bits.
-// Staging: thread (wq, lr) loads row m0 + lr of K11^{-1} and right-hand side col0 + lr
-// at k-slice [8 wq, 8 wq + 8) of the step and stores each as two 16-byte words into the
-// [row][k] stage (k stride kLDK: the 16 lanes of a read hit disjoint banks).  MFMA kk
-// (0..7) of a step takes k = 8 g + kk in lane group g = lane / 16, so a lane reads its
-// eight k of a row as two 16-byte words.  Every output takes the same MFMA sequence at
-// either width, so both widths give the same bits.
+// rows 16 wq .. 16 wq + 15 and all NB blocks of 16 x 16 MFMA outputs, so the rows of
+// K11^{-1} go straight from global memory into the lanes that multiply them: lane (m, g)
+// loads row m0 + 16 wq + m at k = 8 g .. 8 g + 7 of the 32-wide K step, one step ahead.
+// The right-hand sides are shared by the four wavefronts and go through two LDS stages:
+// thread (wq, lr) loads right-hand side col0 + lr at k-slice [8 wq, 8 wq + 8) two steps
+// ahead and stores it into the [column][k] stage (k stride kLDK: the 16 lanes of a read
+// hit disjoint banks) one step ahead, one barrier per step.  MFMA kk (0..7) of a step
+// takes k = 8 g + kk in lane group g.  The even and the odd K steps accumulate apart and
+// are added at the end, so that NG = 2 groups of four wavefronts (512 threads, one group
+// per parity: half the chain of steps, for launches with fewer tiles than compute units)
+// and NG = 1 give the same bits.  Every output takes the same MFMA sequence at either
+// width, so both widths give the same bits.
 constexpr int kW48 = 48;
 constexpr int kLDK = 36;
 // operands are read through the global address space, so that the loads are global (not
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
                                                           const GemmGroup* __restrict__ groups,
                                                           const GemmCol* __restrict__ cols, int accumulate) {
     constexpr int NC = 16 * NB;                         // right-hand sides per tile
-    constexpr int STAGE = (64 + NC) * kLDK;             // floats per stage: A [64][kLDK], B [NC][kLDK]
+    constexpr int STAGE = NC * kLDK;                    // floats per stage: B [NC][kLDK]
     constexpr int NA = 3 - NG;                          // accumulator sets per wavefront: 2 (NG = 1) or 1
     const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
@@ -145,7 +145,8 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
     const ColRef me = col_ref(G, cols, t.col0 + lr, accumulate);
     const gcfloat brow = (gcfloat)me.bf + kq;
     if (!__syncthreads_or(me.live && lr < NC)) return;  // every right-hand side of the tile converged
-    const gcfloat arow = (gcfloat)G.Ahi + (size_t)(t.m0 + lr) * G.ldk + kq;
+    const int m = lane & 15, g8 = (lane >> 4) * 8;
+    const gcfloat arow = (gcfloat)G.Ahi + (size_t)(t.m0 + wq * 16 + m) * G.ldk + g8;
     const int nk = G.ldk / 32;
     const int nsteps = (nk + NG - 1) / NG;              // steps per group (group 1 may idle on the last)
     floatx4 acc[NA][NB];
@@ -153,31 +154,26 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
     for (int h = 0; h < NA; ++h)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[h][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    floatx4 ra0, ra1, rb0, rb1;
-    auto fetch = [&](int s) {                            // group step s is K step NG s + grp
-        const int k0 = min(NG * s + grp, nk - 1) * 32;   // past the last: reload it (unused)
-        ra0 = *(gcfloat4)(arow + k0);
-        ra1 = *(gcfloat4)(arow + k0 + 4);
-        rb0 = *(gcfloat4)(brow + k0);
-        rb1 = *(gcfloat4)(brow + k0 + 4);
+    floatx4 ra0, ra1, ca0, ca1, rb0, rb1;               // A in flight, A of the step, B in flight
+    auto kstep = [&](int s) { return min(NG * s + grp, nk - 1) * 32; };   // past the last: reload it (unused)
+    auto fetchA = [&](int s) {                           // group step s is K step NG s + grp
+        ra0 = *(gcfloat4)(arow + kstep(s));
+        ra1 = *(gcfloat4)(arow + kstep(s) + 4);
+    };
+    auto fetchB = [&](int s) {
+        rb0 = *(gcfloat4)(brow + kstep(s));
+        rb1 = *(gcfloat4)(brow + kstep(s) + 4);
     };
     auto store = [&](int s) {
-        float* As = stg + (s & 1) * STAGE;
-        float* Bs = As + 64 * kLDK;
-        *(floatx4*)(As + lr * kLDK + kq) = ra0;
-        *(floatx4*)(As + lr * kLDK + kq + 4) = ra1;
+        float* Bs = stg + (s & 1) * STAGE;
         if (lr < NC) {
             *(floatx4*)(Bs + lr * kLDK + kq) = rb0;
             *(floatx4*)(Bs + lr * kLDK + kq + 4) = rb1;
         }
     };
     auto mult = [&](int s, floatx4 (&ac)[NB]) {
-        const float* As = stg + (s & 1) * STAGE;
-        const float* Bs = As + 64 * kLDK;
-        const int m = lane & 15, g8 = (lane >> 4) * 8;
-        const floatx4 a0 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8);
-        const floatx4 a1 = *(const floatx4*)(As + (wq * 16 + m) * kLDK + g8 + 4);
-        const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const float* Bs = stg + (s & 1) * STAGE;
+        const float av[8] = {ca0[0], ca0[1], ca0[2], ca0[3], ca1[0], ca1[1], ca1[2], ca1[3]};
         float bv[NB][8];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -197,14 +193,18 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
                 ac[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bv[j][kk], ac[j], 0, 0, 0);
     };
     auto step = [&](int s, floatx4 (&ac)[NB]) {
+        ca0 = ra0;
+        ca1 = ra1;
+        if (s + 1 < nsteps) fetchA(s + 1);
         if (NG == 1 || NG * s + grp < nk) mult(s, ac);
         if (s + 1 < nsteps) store(s + 1);
-        if (s + 2 < nsteps) fetch(s + 2);
+        if (s + 2 < nsteps) fetchB(s + 2);
         __syncthreads();
     };
-    fetch(0);
+    fetchA(0);
+    fetchB(0);
     store(0);
-    if (nsteps > 1) fetch(1);
+    if (nsteps > 1) fetchB(1);
     __syncthreads();
     // two steps per trip, so that each accumulator set is named statically (selecting it by
     // the step's parity copies the accumulators every step: 5% slower, measured)
@@ -257,22 +257,23 @@ __device__ inline void split8x3(const floatx4& x0, const floatx4& x1, ushortx8& 
 // per 16 x 16 block and K step (hh, hm, mh, hl, lh, mm); the dropped terms (ml, lm, ll)
 // are below 2^-23 of |A||B|, so the product carries FP32's precision at BF16 MFMA rates.
 // Tiles, stages and accumulation as in gemm_f32_tile: 64 rows x 16 NB right-hand sides,
-// wavefront wq owns rows 16 wq .. 16 wq + 15, two LDS stages with one barrier per 32-wide
-// K step, the even and the odd steps accumulated apart (NG = 2: one group of four
-// wavefronts per parity, same bits).  Thread (wq, lr) loads the three A terms of row
-// m0 + lr and right-hand side col0 + lr at k-slice [8 wq, 8 wq + 8) and splits the latter
-// on its way into LDS.  Each staged row holds 32 bf16 (64 bytes, no padding) as four
-// 16-byte chunks; chunk c of row r sits at position c ^ ((r >> 2) & 3), so the 16 rows x
-// 4 chunks a wavefront reads for one MFMA operand fall on distinct banks in every group of
-// 16 lanes.  MFMA lane (m, g) takes row m, k = 8 g .. 8 g + 7 of a step.
+// wavefront wq owns rows 16 wq .. 16 wq + 15 and loads the three terms of its rows straight
+// into the MFMA lanes (lane (m, g): row m0 + 16 wq + m, k = 8 g .. 8 g + 7 of the step, one
+// step ahead); the right-hand sides go through two LDS stages with one barrier per 32-wide
+// K step, split into their three terms on the way in (thread (wq, lr): right-hand side
+// col0 + lr, k-slice [8 wq, 8 wq + 8)); the even and the odd steps accumulate apart
+// (NG = 2: one group of four wavefronts per parity, same bits).  Each staged column holds
+// 32 bf16 (64 bytes, no padding) as four 16-byte chunks; chunk c of column r sits at
+// position c ^ ((r >> 2) & 3), so the 16 columns x 4 chunks a wavefront reads for one MFMA
+// operand fall on distinct banks in every group of 16 lanes.
 template <int NB, int NG>
 __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __restrict__ tiles,
                                                            const GemmGroup* __restrict__ groups,
                                                            const GemmCol* __restrict__ cols, int accumulate) {
     constexpr int NC = 16 * NB;
-    constexpr int RW = 32;                              // bf16 per staged row
-    constexpr int PA = 64 * RW, PB = NC * RW;           // one term's plane
-    constexpr int STAGE = 3 * (PA + PB);                // bf16 per stage: Ah Am Al, Bh Bm Bl
+    constexpr int RW = 32;                              // bf16 per staged column
+    constexpr int PB = NC * RW;                         // one term's plane
+    constexpr int STAGE = 3 * PB;                       // bf16 per stage: Bh Bm Bl
     constexpr int NA = 3 - NG;
     const GemmTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const GemmGroup G = groups[t.group];
@@ -284,33 +285,33 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
     const ColRef me = col_ref(G, cols, t.col0 + lr, accumulate);
     const gcfloat brow = (gcfloat)me.bf + kq;
     if (!__syncthreads_or(me.live && lr < NC)) return;  // every right-hand side of the tile converged
-    const size_t aoff = (size_t)(t.m0 + lr) * G.ldk + kq;
+    const int m = lane & 15;
+    const size_t aoff = (size_t)(t.m0 + wq * 16 + m) * G.ldk + (lane >> 4) * 8;
     typedef __attribute__((address_space(1))) const ushortx8* gcush8;
     typedef __attribute__((address_space(1))) const unsigned short* gcush;
     const gcush ah = (gcush)G.Ahi + aoff, am = (gcush)G.Amid + aoff, al = (gcush)G.Alo + aoff;
     const int nk = G.ldk / 32;
     const int nsteps = (nk + NG - 1) / NG;
-    const int wslot = (wq ^ ((lr >> 2) & 3)) * 8;       // this thread's chunk in its staged row
+    const int wslot = (wq ^ ((lr >> 2) & 3)) * 8;       // this thread's chunk in its staged column
     floatx4 acc[NA][NB];
 #pragma unroll
     for (int h = 0; h < NA; ++h)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[h][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    ushortx8 va[3];
-    floatx4 rb0, rb1;
-    auto fetch = [&](int s) {
-        const int k0 = min(NG * s + grp, nk - 1) * 32;   // past the last: reload it (unused)
-        va[0] = *(gcush8)(ah + k0);
-        va[1] = *(gcush8)(am + k0);
-        va[2] = *(gcush8)(al + k0);
-        rb0 = *(gcfloat4)(brow + k0);
-        rb1 = *(gcfloat4)(brow + k0 + 4);
+    ushortx8 va[3], ca[3];                              // A terms in flight, A terms of the step
+    floatx4 rb0, rb1;                                   // B in flight
+    auto kstep = [&](int s) { return min(NG * s + grp, nk - 1) * 32; };   // past the last: reload it (unused)
+    auto fetchA = [&](int s) {
+        va[0] = *(gcush8)(ah + kstep(s));
+        va[1] = *(gcush8)(am + kstep(s));
+        va[2] = *(gcush8)(al + kstep(s));
+    };
+    auto fetchB = [&](int s) {
+        rb0 = *(gcfloat4)(brow + kstep(s));
+        rb1 = *(gcfloat4)(brow + kstep(s) + 4);
     };
     auto store = [&](int s) {
-        unsigned short* As = stg + (s & 1) * STAGE;
-        unsigned short* Bs = As + 3 * PA;
-#pragma unroll
-        for (int p = 0; p < 3; ++p) *(ushortx8*)(As + p * PA + lr * RW + wslot) = va[p];
+        unsigned short* Bs = stg + (s & 1) * STAGE;
         if (lr < NC) {
             ushortx8 b[3];
             split8x3(rb0, rb1, b[0], b[1], b[2]);
@@ -319,13 +320,12 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
         }
     };
     auto mult = [&](int s, floatx4 (&ac)[NB]) {
-        const unsigned short* As = stg + (s & 1) * STAGE;
-        const unsigned short* Bs = As + 3 * PA;
-        const int m = lane & 15, rslot = ((lane >> 4) ^ ((m >> 2) & 3)) * 8;
+        const unsigned short* Bs = stg + (s & 1) * STAGE;
+        const int rslot = ((lane >> 4) ^ ((m >> 2) & 3)) * 8;
         bf16x8 a[3], b[3][NB];
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            a[p] = __builtin_bit_cast(bf16x8, *(const ushortx8*)(As + p * PA + (wq * 16 + m) * RW + rslot));
+            a[p] = __builtin_bit_cast(bf16x8, ca[p]);
 #pragma unroll
             for (int j = 0; j < NB; ++j)
                 b[p][j] = __builtin_bit_cast(bf16x8, *(const ushortx8*)(Bs + p * PB + (j * 16 + m) * RW + rslot));
@@ -339,17 +339,19 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
                 ac[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa[q]], b[pb[q]][j], ac[j], 0, 0, 0);
     };
     auto step = [&](int s, floatx4 (&ac)[NB]) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) ca[p] = va[p];
+        if (s + 1 < nsteps) fetchA(s + 1);
         if (NG == 1 || NG * s + grp < nk) mult(s, ac);
         if (s + 1 < nsteps) store(s + 1);
-        if (s + 2 < nsteps) fetch(s + 2);
+        if (s + 2 < nsteps) fetchB(s + 2);
         __syncthreads();
     };
-    fetch(0);
+    fetchA(0);
+    fetchB(0);
     store(0);
-    if (nsteps > 1) fetch(1);
+    if (nsteps > 1) fetchB(1);
     __syncthreads();
-    // two steps per trip, so that each accumulator set is named statically (a selection by
-    // step parity would copy the accumulators every step)
     // one step per trip (two per trip, as in the FP32 kernel, measured 3-6% slower here)
     for (int s = 0; s < nsteps; ++s) {
         if (NA == 2 && (s & 1)) step(s, acc[NA - 1]);
