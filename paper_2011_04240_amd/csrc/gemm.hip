@@ -154,35 +154,38 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
     for (int h = 0; h < NA; ++h)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[h][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    floatx4 ra0, ra1, ca0, ca1, rb0, rb1;               // A in flight, A of the step, B in flight
+    // two register sets each for A (the step's, the next step's in flight) and B (in
+    // flight to the next stage, being fetched), named statically in a loop of two steps per
+    // trip, so that no loaded register is copied (a copy waits for its load)
+    floatx4 a0[2], a1[2], b0[2], b1[2];
     auto kstep = [&](int s) { return min(NG * s + grp, nk - 1) * 32; };   // past the last: reload it (unused)
-    auto fetchA = [&](int s) {                           // group step s is K step NG s + grp
-        ra0 = *(gcfloat4)(arow + kstep(s));
-        ra1 = *(gcfloat4)(arow + kstep(s) + 4);
+    auto fetchA = [&](int s, floatx4 (&a)[2]) {          // group step s is K step NG s + grp
+        a[0] = *(gcfloat4)(arow + kstep(s));
+        a[1] = *(gcfloat4)(arow + kstep(s) + 4);
     };
-    auto fetchB = [&](int s) {
-        rb0 = *(gcfloat4)(brow + kstep(s));
-        rb1 = *(gcfloat4)(brow + kstep(s) + 4);
+    auto fetchB = [&](int s, floatx4 (&b)[2]) {
+        b[0] = *(gcfloat4)(brow + kstep(s));
+        b[1] = *(gcfloat4)(brow + kstep(s) + 4);
     };
-    auto store = [&](int s) {
+    auto store = [&](int s, const floatx4 (&b)[2]) {
         float* Bs = stg + (s & 1) * STAGE;
         if (lr < NC) {
-            *(floatx4*)(Bs + lr * kLDK + kq) = rb0;
-            *(floatx4*)(Bs + lr * kLDK + kq + 4) = rb1;
+            *(floatx4*)(Bs + lr * kLDK + kq) = b[0];
+            *(floatx4*)(Bs + lr * kLDK + kq + 4) = b[1];
         }
     };
-    auto mult = [&](int s, floatx4 (&ac)[NB]) {
+    auto mult = [&](int s, floatx4 (&ac)[NB], const floatx4 (&a)[2]) {
         const float* Bs = stg + (s & 1) * STAGE;
-        const float av[8] = {ca0[0], ca0[1], ca0[2], ca0[3], ca1[0], ca1[1], ca1[2], ca1[3]};
+        const float av[8] = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
         float bv[NB][8];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const floatx4 b0 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8);
-            const floatx4 b1 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8 + 4);
+            const floatx4 c0 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8);
+            const floatx4 c1 = *(const floatx4*)(Bs + (j * 16 + m) * kLDK + g8 + 4);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                bv[j][e] = b0[e];
-                bv[j][e + 4] = b1[e];
+                bv[j][e] = c0[e];
+                bv[j][e + 4] = c1[e];
             }
         }
         // the NB accumulators interleaved: independent MFMAs back to back
@@ -192,28 +195,25 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
             for (int j = 0; j < NB; ++j)
                 ac[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bv[j][kk], ac[j], 0, 0, 0);
     };
-    auto step = [&](int s, floatx4 (&ac)[NB]) {
-        ca0 = ra0;
-        ca1 = ra1;
-        if (s + 1 < nsteps) fetchA(s + 1);
-        if (NG == 1 || NG * s + grp < nk) mult(s, ac);
-        if (s + 1 < nsteps) store(s + 1);
-        if (s + 2 < nsteps) fetchB(s + 2);
+    auto step = [&](int s, floatx4 (&ac)[NB], const floatx4 (&acur)[2], floatx4 (&anext)[2],
+                    const floatx4 (&bstore)[2], floatx4 (&bfetch)[2]) {
+        fetchA(s + 1, anext);                            // unconditional: past the end it reloads
+        if (NG == 1 || NG * s + grp < nk) mult(s, ac, acur);    // the last step, so that the
+        if (s + 1 < nsteps) store(s + 1, bstore);              // count of loads in flight is the
+        fetchB(s + 2, bfetch);                                 // same on every path
         __syncthreads();
     };
-    fetchA(0);
-    fetchB(0);
-    store(0);
-    if (nsteps > 1) fetchB(1);
+    fetchA(0, a0);
+    fetchB(0, b0);
+    store(0, b0);
+    fetchB(1, b1);
     __syncthreads();
-    // two steps per trip, so that each accumulator set is named statically (selecting it by
-    // the step's parity copies the accumulators every step: 5% slower, measured)
     int s = 0;
     for (; s + 1 < nsteps; s += 2) {
-        step(s, acc[0]);
-        step(s + 1, acc[NA - 1]);
+        step(s, acc[0], a0, a1, b1, b0);
+        step(s + 1, acc[NA - 1], a1, a0, b0, b1);
     }
-    if (s < nsteps) step(s, acc[0]);
+    if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
     // the odd steps' partial tile: the second accumulator set, or group 1's through LDS (the
     // stages are free after the last barrier); even + odd, then c (+)= result
     float* red = smem;
@@ -298,28 +298,29 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
     for (int h = 0; h < NA; ++h)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[h][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    ushortx8 va[3], ca[3];                              // A terms in flight, A terms of the step
-    floatx4 rb0, rb1;                                   // B in flight
+    // register sets named statically in a loop of two steps per trip, as in gemm_f32_tile
+    ushortx8 a0[3], a1[3];                              // A terms: the step's, the next step's
+    floatx4 b0[2], b1[2];                               // B: to the next stage, being fetched
     auto kstep = [&](int s) { return min(NG * s + grp, nk - 1) * 32; };   // past the last: reload it (unused)
-    auto fetchA = [&](int s) {
-        va[0] = *(gcush8)(ah + kstep(s));
-        va[1] = *(gcush8)(am + kstep(s));
-        va[2] = *(gcush8)(al + kstep(s));
+    auto fetchA = [&](int s, ushortx8 (&a)[3]) {
+        a[0] = *(gcush8)(ah + kstep(s));
+        a[1] = *(gcush8)(am + kstep(s));
+        a[2] = *(gcush8)(al + kstep(s));
     };
-    auto fetchB = [&](int s) {
-        rb0 = *(gcfloat4)(brow + kstep(s));
-        rb1 = *(gcfloat4)(brow + kstep(s) + 4);
+    auto fetchB = [&](int s, floatx4 (&b)[2]) {
+        b[0] = *(gcfloat4)(brow + kstep(s));
+        b[1] = *(gcfloat4)(brow + kstep(s) + 4);
     };
-    auto store = [&](int s) {
+    auto store = [&](int s, const floatx4 (&b)[2]) {
         unsigned short* Bs = stg + (s & 1) * STAGE;
         if (lr < NC) {
-            ushortx8 b[3];
-            split8x3(rb0, rb1, b[0], b[1], b[2]);
+            ushortx8 t3[3];
+            split8x3(b[0], b[1], t3[0], t3[1], t3[2]);
 #pragma unroll
-            for (int p = 0; p < 3; ++p) *(ushortx8*)(Bs + p * PB + lr * RW + wslot) = b[p];
+            for (int p = 0; p < 3; ++p) *(ushortx8*)(Bs + p * PB + lr * RW + wslot) = t3[p];
         }
     };
-    auto mult = [&](int s, floatx4 (&ac)[NB]) {
+    auto mult = [&](int s, floatx4 (&ac)[NB], const ushortx8 (&ca)[3]) {
         const unsigned short* Bs = stg + (s & 1) * STAGE;
         const int rslot = ((lane >> 4) ^ ((m >> 2) & 3)) * 8;
         bf16x8 a[3], b[3][NB];
@@ -338,25 +339,25 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
             for (int j = 0; j < NB; ++j)
                 ac[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa[q]], b[pb[q]][j], ac[j], 0, 0, 0);
     };
-    auto step = [&](int s, floatx4 (&ac)[NB]) {
-#pragma unroll
-        for (int p = 0; p < 3; ++p) ca[p] = va[p];
-        if (s + 1 < nsteps) fetchA(s + 1);
-        if (NG == 1 || NG * s + grp < nk) mult(s, ac);
-        if (s + 1 < nsteps) store(s + 1);
-        if (s + 2 < nsteps) fetchB(s + 2);
+    auto step = [&](int s, floatx4 (&ac)[NB], const ushortx8 (&acur)[3], ushortx8 (&anext)[3],
+                    const floatx4 (&bstore)[2], floatx4 (&bfetch)[2]) {
+        fetchA(s + 1, anext);                            // unconditional: past the end it reloads
+        if (NG == 1 || NG * s + grp < nk) mult(s, ac, acur);    // the last step, so that the
+        if (s + 1 < nsteps) store(s + 1, bstore);              // count of loads in flight is the
+        fetchB(s + 2, bfetch);                                 // same on every path
         __syncthreads();
     };
-    fetchA(0);
-    fetchB(0);
-    store(0);
-    if (nsteps > 1) fetchB(1);
+    fetchA(0, a0);
+    fetchB(0, b0);
+    store(0, b0);
+    fetchB(1, b1);
     __syncthreads();
-    // one step per trip (two per trip, as in the FP32 kernel, measured 3-6% slower here)
-    for (int s = 0; s < nsteps; ++s) {
-        if (NA == 2 && (s & 1)) step(s, acc[NA - 1]);
-        else step(s, acc[0]);
+    int s = 0;
+    for (; s + 1 < nsteps; s += 2) {
+        step(s, acc[0], a0, a1, b1, b0);
+        step(s + 1, acc[NA - 1], a1, a0, b0, b1);
     }
+    if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
     float* red = reinterpret_cast<float*>(smem);
     if (NG == 2) {
         if (grp == 1) {
