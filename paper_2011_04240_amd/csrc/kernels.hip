@@ -630,10 +630,19 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     const WorkItem it = items[xcd_tile(blockIdx.x, gridDim.x)];
     const ProblemDesc<S>* __restrict__ Dp = probs + it.prob;
     gptr<const int> ctrl = glob((const int*)Dp->ctrl);
-    if (!ctrl[3]) return;                          // inactive slot
-    if (MODE == kModeIter && ctrl[1]) return;      // converged
     const int n = Dp->n, np = Dp->np, n_obs = OBS ? Dp->n_obs : 0;
     const int t0 = it.t0, tc = it.tc;
+    const int nv = NV > 0 ? NV : Dp->nv;
+    const int ngr = (np + 63) >> 6;                                      // 64-row multiplier groups
+    // The first basis entry and group flag of each thread are requested before the activity
+    // test, so that their latency overlaps it (dropped if the slot is idle).
+    const int tid = threadIdx.x;
+    gptr<const double> Pm = glob(Dp->P);
+    gptr<unsigned> lflag = glob(Dp->lflag);
+    const double p_first = tid < tc * nv ? Pm[(size_t)t0 * nv + tid] : 0.0;
+    const unsigned f_first = (MODE == kModeIter && tid < tc * ngr) ? lflag[(size_t)t0 * ngr + tid] : 0u;
+    if (!ctrl[3]) return;                          // inactive slot
+    if (MODE == kModeIter && ctrl[1]) return;      // converged
     gptr<const unsigned> pairs = glob(Dp->pairs);
     gptr<S> lam = glob(Dp->lam);
     gptr<S> ssum = glob(Dp->ssum);
@@ -648,8 +657,6 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     const S irho_b = (MODE == kModeIter && Dp->switch_at > 0 && ctrl[0] + 1 == Dp->switch_at) ? Dp->sirho_next : irho;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nv = NV > 0 ? NV : Dp->nv;
-    const int ngr = (np + 63) >> 6;                                      // 64-row multiplier groups
     float4* Xs = reinterpret_cast<float4*>(smem_raw);                     // [tc][n]
     long long* Acc = reinterpret_cast<long long*>(Xs + (size_t)tc * n);  // [tc][3][n], first [tc][nv] doubles
     unsigned long long* Fb = reinterpret_cast<unsigned long long*>(Acc + (size_t)tc * max(3 * n, nv));  // [ngr]
@@ -661,7 +668,6 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     unsigned* Lq = reinterpret_cast<unsigned*>(Bs + (size_t)n * 6);     // [BLOCK/64][64][2] row lists
     __shared__ int any_general;                    // some row took the general branch (iteration)
     __shared__ int wcnt[BLOCK / 64];
-    const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
 
     int pw = 64;
@@ -686,7 +692,6 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
     // decides whether its multipliers are read.  A group read as 0 takes out-of-range buffer
     // offsets, which return +0 without a memory access.
     const int wrow = __builtin_amdgcn_readfirstlane(pl & ~63);
-    gptr<unsigned> lflag = glob(Dp->lflag);
 
     unsigned code[U], Fl[U] = {0u, 0u, 0u, 0u};
     S L[U][3], Q[U][3];
@@ -739,12 +744,14 @@ __global__ __launch_bounds__(BLOCK) void pairwise_fx_kernel(const WorkItem* __re
         // coefficients sit in registers and G = BLOCK / 3n thread groups take every G-th
         // instant, two instants' products in flight at a time.
         gptr<const double> cm = glob((const double*)Dp->c);
-        gptr<const double> Pm = glob(Dp->P);
         const int ldc = Dp->ldc;
         double* Pl = reinterpret_cast<double*>(Acc);                    // [tc][nv]
-        for (int idx = tid; idx < tc * nv; idx += BLOCK) Pl[idx] = Pm[(size_t)t0 * nv + idx];
-        if (MODE == kModeIter)
-            for (int idx = tid; idx < tc * ngr; idx += BLOCK) Fs[idx] = lflag[(size_t)t0 * ngr + idx];
+        if (tid < tc * nv) Pl[tid] = p_first;
+        for (int idx = tid + BLOCK; idx < tc * nv; idx += BLOCK) Pl[idx] = Pm[(size_t)t0 * nv + idx];
+        if (MODE == kModeIter) {
+            if (tid < tc * ngr) Fs[tid] = f_first;
+            for (int idx = tid + BLOCK; idx < tc * ngr; idx += BLOCK) Fs[idx] = lflag[(size_t)t0 * ngr + idx];
+        }
         __syncthreads();
         if (nit > 0) fetch(0, 0, first0);
         float* Xf = reinterpret_cast<float*>(Xs);
