@@ -15,7 +15,8 @@
 //                    residual record (max ||f_c||, rms, smoothness cost) and the
 //                    convergence test.
 //   residual_kernel  FP64 refinement residual g - H c of eq. (kkt_step_x), with
-//                    H c = (I (x) Pdd^T Pdd) c + rho (((n + n_obs) I - 1 1^T) (x) P^T P) c.
+//                    H c = (I (x) Pdd^T Pdd) c + rho (((n + n_obs) I - 1 1^T) (x) P^T P) c,
+//                    stored as the correction's product reads it (FP64, or rounded to FP32).
 //   ceq_kernel       c_eq = K12^{-1} b_eq, the boundary part of the inverse product.
 //   init_kernel      boundary-only minimum-acceleration coefficients (initialisation).
 //
@@ -1530,8 +1531,8 @@ __global__ __launch_bounds__(256) void residual_kernel(const ProblemDesc<S>* __r
         for (int l = 0; l < nv; ++l)
             h += PddtPdd[k * nv + l] * ci[l] + PtP[k * nv + l] * (nr * ci[l] - rho * csum[l]);
         const double v = q[o] - h;
-        r[o] = v;
-        rf[o] = (float)v;
+        if constexpr (std::is_same<S, double>::value) r[o] = v;    // the FP64 product's operand
+        else rf[o] = (float)v;                                     // the MFMA products' operand
     }
 }
 
