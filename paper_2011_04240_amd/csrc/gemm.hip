@@ -73,37 +73,38 @@ __device__ inline unsigned long long shfl_u64(unsigned long long x, int from) {
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// c (+)= v for the NB 16 x 16 blocks of wavefront wq: lane (m, g) holds rows
-// m0 + 16 wq + 4 g + r (r = 0..3) of right-hand side col0 + 16 j + m.  The column's
-// pointers come from lane 16 j + m, which loaded them in the prologue, and the old values
-// of all blocks are requested together (rows past M clamped, their results dropped): one
-// memory latency at the end of the tile instead of a chain of dependent loads per block.
+// The output of wavefront wq is NB 16 x 16 blocks: lane (m, g) holds rows
+// m0 + 16 wq + 4 g + r (r = 0..3) of right-hand side col0 + 16 j + m.  A column's pointers
+// come from lane 16 j + m, which loaded them in the prologue.  load_old requests the values
+// the product is added to for all blocks together (rows past M clamped, their results
+// dropped) at the start of the last K step, so that they arrive while it runs; store_tile
+// writes c = old + v.
 template <int NB>
-__device__ inline void store_tile(const GemmTile& t, const GemmGroup& G, const ColRef& me, int wq, int lane,
-                                  const float (&v)[NB][4]) {
+__device__ inline void load_old(const GemmTile& t, const GemmGroup& G, const ColRef& me, int wq, int lane,
+                                double (&old)[NB][4]) {
     const int m = lane & 15, g = lane >> 4;
-    double* dst[NB];
-    const double* src[NB];
-    int live[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-        const int from = j * 16 + m;
-        dst[j] = (double*)shfl_u64((unsigned long long)me.c, from);
-        src[j] = (const double*)shfl_u64((unsigned long long)me.src, from);
-        live[j] = __shfl(me.live, from);
+        const double* src = (const double*)shfl_u64((unsigned long long)me.src, j * 16 + m);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) old[j][r] = src[min(t.m0 + wq * 16 + 4 * g + r, G.M - 1)];
     }
-    double old[NB][4];
+}
+
+template <int NB>
+__device__ inline void store_tile(const GemmTile& t, const GemmGroup& G, const ColRef& me, int wq, int lane,
+                                  const double (&old)[NB][4], const float (&v)[NB][4]) {
+    const int m = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) old[j][r] = src[j][min(t.m0 + wq * 16 + 4 * g + r, G.M - 1)];
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NB; ++j) {
+        double* dst = (double*)shfl_u64((unsigned long long)me.c, j * 16 + m);
+        const int live = __shfl(me.live, j * 16 + m);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = t.m0 + wq * 16 + 4 * g + r;
-            if (live[j] && row < G.M) dst[j][row] = old[j][r] + (double)v[j][r];
+            if (live && row < G.M) dst[row] = old[j][r] + (double)v[j][r];
         }
+    }
 }
 
 // FP32 product over tiles of 64 rows x 16 NB right-hand sides (NB = 4: 64, NB = 3: 48,
@@ -208,12 +209,31 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
     store(0, b0);
     fetchB(1, b1);
     __syncthreads();
+    // the last step is taken after the addends of the epilogue are requested (48-column
+    // tiles; at 64 columns their registers would cost a wavefront per SIMD)
+    double old[NB][4];
     int s = 0;
-    for (; s + 1 < nsteps; s += 2) {
-        step(s, acc[0], a0, a1, b1, b0);
-        step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+    if constexpr (NB == 3) {
+        for (; s + 2 < nsteps; s += 2) {
+            step(s, acc[0], a0, a1, b1, b0);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        }
+        if (s + 1 < nsteps) {
+            step(s, acc[0], a0, a1, b1, b0);
+            load_old<NB>(t, G, me, wq, lane, old);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        } else {
+            load_old<NB>(t, G, me, wq, lane, old);
+            step(s, acc[0], a0, a1, b1, b0);
+        }
+    } else {
+        for (; s + 1 < nsteps; s += 2) {
+            step(s, acc[0], a0, a1, b1, b0);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        }
+        if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
+        load_old<NB>(t, G, me, wq, lane, old);
     }
-    if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
     // the odd steps' partial tile: the second accumulator set, or group 1's through LDS (the
     // stages are free after the last barrier); even + odd, then c (+)= result
     float* red = smem;
@@ -233,7 +253,7 @@ __global__ __launch_bounds__(256 * NG) void gemm_f32_tile(const GemmTile* __rest
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             v[j][r] = acc[0][j][r] + (NG == 2 ? red[((wq * NB + j) * 4 + r) * 64 + lane] : acc[NA - 1][j][r]);
-    store_tile<NB>(t, G, me, wq, lane, v);
+    store_tile<NB>(t, G, me, wq, lane, old, v);
 }
 
 // The three BF16 terms of eight FP32 values, hi = bf16(x), mid = bf16(x - hi),
@@ -352,12 +372,31 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
     store(0, b0);
     fetchB(1, b1);
     __syncthreads();
+    // the last step is taken after the addends of the epilogue are requested (48-column
+    // tiles; at 64 columns their registers would cost a wavefront per SIMD)
+    double old[NB][4];
     int s = 0;
-    for (; s + 1 < nsteps; s += 2) {
-        step(s, acc[0], a0, a1, b1, b0);
-        step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+    if constexpr (NB == 3) {
+        for (; s + 2 < nsteps; s += 2) {
+            step(s, acc[0], a0, a1, b1, b0);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        }
+        if (s + 1 < nsteps) {
+            step(s, acc[0], a0, a1, b1, b0);
+            load_old<NB>(t, G, me, wq, lane, old);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        } else {
+            load_old<NB>(t, G, me, wq, lane, old);
+            step(s, acc[0], a0, a1, b1, b0);
+        }
+    } else {
+        for (; s + 1 < nsteps; s += 2) {
+            step(s, acc[0], a0, a1, b1, b0);
+            step(s + 1, acc[NA - 1], a1, a0, b0, b1);
+        }
+        if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
+        load_old<NB>(t, G, me, wq, lane, old);
     }
-    if (s < nsteps) step(s, acc[0], a0, a1, b1, b0);
     float* red = reinterpret_cast<float*>(smem);
     if (NG == 2) {
         if (grp == 1) {
@@ -375,7 +414,7 @@ __global__ __launch_bounds__(256 * NG) void gemm_bf16_tile(const GemmTile* __res
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             v[j][r] = acc[0][j][r] + (NG == 2 ? red[((wq * NB + j) * 4 + r) * 64 + lane] : acc[NA - 1][j][r]);
-    store_tile<NB>(t, G, me, wq, lane, v);
+    store_tile<NB>(t, G, me, wq, lane, old, v);
 }
 
 __global__ __launch_bounds__(256) void gemm_f64(const GemmTile* __restrict__ tiles,
