@@ -1442,12 +1442,20 @@ __global__ __launch_bounds__(256) void qbuild_kernel(const ProblemDesc<S>* __res
                 double cv[NV];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) cv[k] = ci[k];
+                // FP32 problems: the column's own copy in LDS (its slot of the staged positions
+                // part, no longer read) for the loop over k (not unrolled), an LDS read per k
+                // instead of a global one
+                double* cl = kCorr ? cxs + (size_t)col * NV : nullptr;
+                if constexpr (kCorr) {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) cl[k] = cv[k];
+                }
 #pragma unroll 1
                 for (int k = 0; k < NV; ++k) {
                     double gk = 0.0;
 #pragma unroll
                     for (int l = 0; l < NV; ++l) gk += G[k * NV + l] * cv[l];
-                    z += ci[k] * gk;                 // ci[k] == cv[k], read from memory (k not unrolled)
+                    z += (kCorr ? cl[k] : (double)ci[k]) * gk;    // == cv[k]
                 }
             } else {
                 for (int k = 0; k < nv; ++k) {
